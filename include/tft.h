@@ -1,0 +1,201 @@
+/*
+ * tft.h -- C ABI of the MI355X (gfx950) truncated FFT library.
+ *
+ * The library computes the truncated Fourier transform (TFT) and its inverse
+ * (ITFT) of D. Harvey, "A cache-friendly truncated FFT", in the paper's
+ * Bailey-style 2^l1 x 2^l2 row/column order (Sect. 3, Alg. 1; Sect. 4, Alg. 2),
+ * the pointwise products between them (Sect. 2), and the two products built on
+ * them: Schoenhage-Strassen in Z[x] (Sect. 5.1) and Schoenhage-Nussbaumer in
+ * (Z/mZ)[x] (Sect. 5.2).
+ *
+ * Conventions shared by every entry point
+ *   - Every pointer named x, a, b, c, g, h, out is DEVICE memory owned by the
+ *     caller.  The library never frees caller memory.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *     asynchronous on that stream; a device fault surfaces at a later call or
+ *     synchronisation and is reported as TFT_E_DEVICE.
+ *   - On any argument error nothing is launched and nothing is written.
+ *   - zeta is passed as an exponent s: zeta = theta^s (Sect. 6), with theta
+ *     the ring's shift unit (2 in Z/(2^N+1), y in (Z/mZ)[y]/(y^K+1)).
+ *   - Reentrant for distinct buffers and streams.  The first call with a new
+ *     shape builds and uploads a plan (host work plus hipMalloc of a few KB of
+ *     descriptors); later calls with that shape allocate nothing.
+ *
+ * Cell arrays (the array x_0..x_{L-1} of Sect. 2, "Algorithms 1 and 2 operate
+ * on an array x_0, ..., x_{L-1}")
+ *   FERMAT ring Z/(2^N+1), W = N/32 limbs: an array of C cells is C*W uint32
+ *     limbs (cell i at limbs [i*W, (i+1)*W), little-endian) followed by C
+ *     uint32 "top" words (cell i's top at index C*W + i).  Cell value =
+ *     limbs + top * 2^N; canonical cells lie in [0, 2^N] (top = 1 only for
+ *     the residue 2^N, with all limbs zero).  Inputs must be canonical;
+ *     outputs are canonical.  Total bytes: C * (W+1) * 4.
+ *   NEGA ring (Z/mZ)[y]/(y^K+1): an array of C cells is C*K uint64
+ *     coefficients (cell i at [i*K, (i+1)*K), coefficient of y^j at j),
+ *     each in [0, m).  Total bytes: C * K * 8.
+ */
+#ifndef TFT_H
+#define TFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TFT_OK = 0,
+    TFT_E_ARG = 1,         /* a size, length or flag violates the stated ranges */
+    TFT_E_RING = 2,        /* ring unsupported or theta has no power of the needed order */
+    TFT_E_RANGE = 3,       /* an output does not fit in the limbs the caller gave */
+    TFT_E_WORKSPACE = 4,   /* workspace pointer NULL or smaller than required */
+    TFT_E_DEVICE = 5,      /* a HIP call failed (launch error, fault, no device) */
+    TFT_E_UNSUPPORTED = 6  /* valid request outside what this build implements */
+} tft_status;
+
+enum { TFT_RING_FERMAT = 1, TFT_RING_NEGA = 2 };
+
+/* The coefficient ring R of Sect. 2.
+ *   kind = TFT_RING_FERMAT: R = Z/(2^N+1), theta = 2 of order 2N (Sect. 2 example,
+ *          Sect. 5.1).  This build needs N = 32*W with W a power of two, 1 <= W <= 4096.
+ *   kind = TFT_RING_NEGA:   R = (Z/mZ)[y]/(y^K+1), theta = y of order 2K (Sect. 5.2).
+ *          This build needs K a power of two, 2 <= K <= 4096, and m odd, 3 <= m < 2^62.
+ * Unused fields must be zero. */
+typedef struct {
+    uint32_t kind;
+    uint32_t N;
+    uint32_t K;
+    uint32_t reserved;
+    uint64_t m;
+} tft_ring;
+
+/* Split policy for the Bailey decomposition (Sect. 2: L = L1 L2).
+ * top_l1     log2 of L1 at the top level; 0 = the paper's floor(l/2) (Alg. 1, Alg. 2).
+ * leaf_log2  log2 of the largest sub-transform run inside one workgroup's LDS;
+ *            0 = the largest that fits.  Every split gives identical outputs. */
+typedef struct {
+    uint32_t top_l1;
+    uint32_t leaf_log2;
+} tft_split;
+
+/* Human-readable name of a status code (static string). */
+const char *tft_status_string(int status);
+
+/* TFT_OK if the ring is supported by this build (see tft_ring). */
+int tft_ring_check(const tft_ring *ring);
+
+/* Bytes of one cell of `ring` (FERMAT: 4*(N/32+1), NEGA: 8*K); 0 if unsupported. */
+uint64_t tft_elem_bytes(const tft_ring *ring);
+
+/* Bytes of a cell array with `cells` cells (layout above). 0 if unsupported. */
+uint64_t tft_array_bytes(const tft_ring *ring, uint64_t cells);
+
+/* TFT(L, zeta, z, n) of Sect. 2 computed in place by Alg. 1 (Sect. 3).
+ *   l       transform length L = 2^l, 1 <= l <= 24; L must divide ord(theta).
+ *   s       zeta = theta^s (any s; taken mod ord(theta)).
+ *   z, n    1 <= z <= L, 1 <= n <= L.
+ *   x       cell array of capacity L.  Cells [0, z) hold a_0..a_{z-1}; cells
+ *           >= z are never read (a_i = 0 there) and may hold anything.
+ * On return cells [0, n) hold a_hat_0..a_hat_{n-1} of eq. (1); all other
+ * cells are clobbered (Sect. 2: every cell may serve as scratch). */
+int tft_forward(const tft_ring *ring, uint32_t l, uint64_t s, uint64_t z, uint64_t n, void *x, void *stream);
+
+/* ITFT(L, zeta, z, n, f) of Sect. 2 computed in place by Alg. 2 (Sect. 4).
+ *   f in {0, 1}; 1 <= z <= L; z >= n; 1 <= n + f <= L.
+ *   x       cell array of capacity L: cells [0, n) hold a_hat_0..a_hat_{n-1},
+ *           cells [n, z) hold L*a_n..L*a_{z-1}; cells >= z are never read.
+ * On return cells [0, n) hold L*a_0..L*a_{n-1} (NOT divided by L) and, if
+ * f = 1, cell n holds a_hat_n; every other cell is clobbered. */
+int itft_inverse(const tft_ring *ring, uint32_t l, uint64_t s, uint64_t z, uint64_t n, uint32_t f, void *x,
+                 void *stream);
+
+/* Pointwise products (Sect. 2: u_hat_i = g_hat_i h_hat_i, 0 <= i < n):
+ *   c_i = a_i * b_i * 2^(-scale_log2) in R for 0 <= i < n.
+ * a, b, c are cell arrays of capacity `cap` (n <= cap); c may alias a or b.
+ * scale_log2 folds the division by L = 2^l that the ITFT leaves (Sect. 2). */
+int pointwise_mul(const tft_ring *ring, uint64_t n, const void *a, const void *b, void *c, uint64_t cap,
+                  uint32_t scale_log2, void *stream);
+
+/* Parameters of a Schoenhage-Strassen product; NULL means the defaults.
+ *   N      ring Z/(2^N+1); 0 = smallest supported N holding every output coefficient.
+ *   l      transform length 2^l; 0 = smallest with 2^l >= len_g + len_h - 1.
+ *   split  Bailey split policy (top_l1 = leaf_log2 = 0: paper split, largest leaf). */
+typedef struct {
+    uint32_t N;
+    uint32_t l;
+    tft_split split;
+} tft_ss_params;
+
+/* Workspace bytes zx_mul_ss needs for these operand shapes and parameters. */
+int zx_mul_ss_workspace(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h_limbs,
+                        const tft_ss_params *params, uint64_t *bytes);
+
+/* Product u = g h in Z[x] by Schoenhage-Strassen over R = Z/(2^N+1) (Sect. 5.1):
+ * pack, TFT(g), TFT(h) (Sect. 2, zeta = 1), n = len_g + len_h - 1 pointwise
+ * products with 2^-l folded in, ITFT(L, 1, n, n, 0), unpack.
+ *   g      len_g coefficients, g_limbs uint32 limbs each (little-endian), non-negative.
+ *   h      len_h coefficients, h_limbs limbs each.
+ *   out    len_g + len_h - 1 coefficients, out_limbs limbs each.
+ * Needs out_limbs*32 >= 32*(g_limbs + h_limbs) + ceil(log2 min(len_g, len_h)),
+ * else TFT_E_RANGE.  ws: device workspace of at least zx_mul_ss_workspace bytes. */
+int zx_mul_ss(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uint32_t *h, uint64_t len_h,
+              uint32_t h_limbs, uint32_t *out, uint32_t out_limbs, const tft_ss_params *params, void *ws,
+              uint64_t ws_bytes, void *stream);
+
+/* Workspace bytes zmx_mul_nussbaumer needs. */
+int zmx_mul_nussbaumer_workspace(uint64_t len_g, uint64_t len_h, uint32_t log2K, uint64_t *bytes);
+
+/* Product u = g h in (Z/mZ)[x] by Schoenhage-Nussbaumer (Sect. 5.2): the
+ * inputs are cut into pieces of K/2 coefficients placed in the low half of
+ * elements of R = (Z/mZ)[y]/(y^K+1), multiplied through TFT/TFT/pointwise
+ * negacyclic products/ITFT over R with theta = y, and recombined by adding
+ * the overlapping pieces mod m.
+ *   g, h   len_g, len_h coefficients (uint64, each < m); m odd, 3 <= m < 2^62.
+ *   log2K  K = 2^log2K, 1 <= log2K <= 12; the transform length 2^l is the
+ *          smallest power of two >= (pieces of g) + (pieces of h) - 1 and must
+ *          not exceed 2K, else TFT_E_ARG.
+ *   out    len_g + len_h - 1 coefficients (uint64, in [0, m)). */
+int zmx_mul_nussbaumer(const uint64_t *g, uint64_t len_g, const uint64_t *h, uint64_t len_h, uint64_t m,
+                       uint32_t log2K, uint64_t *out, void *ws, uint64_t ws_bytes, void *stream);
+
+/* ---- explicit plans: transforms with a chosen split, built ahead of use ---- */
+
+typedef struct tft_plan tft_plan;
+
+/* Build the pass schedule of one transform (direction 0 = TFT, 1 = ITFT) on
+ * the host.  Pure host work: needs no GPU.  f is ignored for the TFT. */
+int tft_plan_create(const tft_ring *ring, uint32_t direction, uint32_t l, uint64_t s, uint64_t z, uint64_t n,
+                    uint32_t f, const tft_split *split, tft_plan **plan);
+
+/* Run a plan in place on cell array x (capacity 2^l) on `stream`.  The first
+ * execution uploads the plan's descriptors. */
+int tft_plan_execute(tft_plan *plan, void *x, void *stream);
+
+/* Free a plan (host and device descriptors).  NULL is ignored. */
+void tft_plan_destroy(tft_plan *plan);
+
+/* Number of base-case (L = 2) executions the plan performs, counting
+ * executions that change nothing, as in Theorems 1 and 2. */
+uint64_t tft_plan_base_cases(const tft_plan *plan);
+
+/* Serialise the plan's schedule into `buf` (uint64 words) for host-side
+ * inspection.  *needed receives the word count; if cap_words is too small
+ * nothing is written and TFT_E_ARG is returned.  Layout:
+ *   [0] version (1)  [1] passes  [2] jobs  [3] programs  [4] steps  [5] ops
+ *   [6] ord(theta)   [7] leaf_log2
+ *   passes:   per pass   job_begin, job_count, max_len
+ *   jobs:     per job    base, stride, program, s, nload, nstore
+ *   programs: per prog   step_begin, step_count, len
+ *   steps:    per step   op_begin, op_count
+ *   ops:      per op     opcode, i0, i1, alog, b   (exponent = s * 2^alog + b mod ord)
+ * Opcodes: 0 none, 1 TFT z=2 n=2, 2 TFT z=1 n=2, 3 TFT z=2 n=1,
+ *          4 ITFT n=2, 5 ITFT n=1 f=1 z=2, 6 ITFT n=1 f=1 z=1, 7 ITFT n=1 f=0 z=2,
+ *          8 ITFT n=1 f=0 z=1, 9 ITFT n=0 z=2, 10 ITFT n=0 z=1
+ * (the base cases of Alg. 1 and Alg. 2, L = 2). */
+int tft_plan_export(const tft_plan *plan, uint64_t *buf, uint64_t cap_words, uint64_t *needed);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TFT_H */

@@ -78,8 +78,12 @@ class FermatRing:
         return pow(2, e % self.ord, self.p)
 
     def mul_theta(self, a, e: int):
-        """a * theta^e."""
-        return (a * self.theta_pow(e)) % self.p
+        """a * 2^e, reduced with 2^N = -1: a 2^t = hi 2^N + lo = lo - hi, and 2^(N+t) = -2^t."""
+        e %= self.ord
+        neg = e >= self.N
+        x = (a % self.p) << (e - self.N if neg else e)
+        r = ((x & ((1 << self.N) - 1)) - (x >> self.N)) % self.p
+        return (-r) % self.p if neg else r
 
     def inv_pow2(self, k: int):
         """2^-k in R (2 is invertible: 2 * 2^(2N-1) = 2^(2N) = 1)."""
@@ -140,7 +144,17 @@ class NegaRing:
         return tuple(v)
 
     def mul_theta(self, a, e: int):
-        return self.mul(a, self.theta_pow(e))
+        """a * y^e: coefficient i moves to i + e; passing y^K flips its sign (y^K = -1)."""
+        K, m = self.K, self.m
+        out = [0] * K
+        for i, x in enumerate(a):
+            pos = i + (e % self.ord)
+            sign = 1
+            while pos >= K:
+                pos -= K
+                sign = -sign
+            out[pos] = (sign * x) % m
+        return tuple(out)
 
     def inv_pow2(self, k: int):
         v = [0] * self.K

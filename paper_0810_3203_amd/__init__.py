@@ -1,0 +1,37 @@
+"""MI355X (gfx950) truncated FFT library: Python binding of ``include/tft.h``.
+
+Argument marshalling only: every step of the transforms and products runs in
+the HIP kernels of ``libtft.so``.  PyTorch provides device memory and streams.
+The binding never computes a result itself; if the shared library is missing
+it raises instead of falling back to anything else.
+"""
+
+from ._binding import (  # noqa: F401
+    FERMAT,
+    NEGA,
+    Plan,
+    SSParams,
+    Split,
+    TFTError,
+    array_bytes,
+    elem_bytes,
+    fermat_ring,
+    itft_inverse,
+    lib,
+    lib_path,
+    nega_ring,
+    pointwise_mul,
+    ring_check,
+    status_string,
+    tft_forward,
+    zmx_mul_nussbaumer,
+    zmx_mul_nussbaumer_workspace,
+    zx_mul_ss,
+    zx_mul_ss_workspace,
+)
+
+__all__ = [
+    "FERMAT", "NEGA", "Plan", "SSParams", "Split", "TFTError", "array_bytes", "elem_bytes", "fermat_ring",
+    "itft_inverse", "lib", "lib_path", "nega_ring", "pointwise_mul", "ring_check", "status_string", "tft_forward",
+    "zmx_mul_nussbaumer", "zmx_mul_nussbaumer_workspace", "zx_mul_ss", "zx_mul_ss_workspace",
+]

@@ -1,0 +1,238 @@
+"""ctypes binding of libtft.so with the C names of include/tft.h.
+
+Device buffers are torch tensors (their data_ptr() is passed through); streams
+are torch streams (cuda_stream handle), defaulting to the current stream.
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(HERE, "libtft.so")
+
+FERMAT = 1
+NEGA = 2
+
+_STATUS_NAMES = {0: "TFT_OK", 1: "TFT_E_ARG", 2: "TFT_E_RING", 3: "TFT_E_RANGE", 4: "TFT_E_WORKSPACE",
+                 5: "TFT_E_DEVICE", 6: "TFT_E_UNSUPPORTED"}
+
+
+class TFTError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__("%s: %s (%s)" % (where, status_string(status), _STATUS_NAMES.get(status, status)))
+
+
+class Ring(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("N", ctypes.c_uint32), ("K", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("m", ctypes.c_uint64)]
+
+    def __repr__(self):
+        if self.kind == FERMAT:
+            return "Ring(Z/(2^%d+1))" % self.N
+        return "Ring((Z/%dZ)[y]/(y^%d+1))" % (self.m, self.K)
+
+
+class Split(ctypes.Structure):
+    _fields_ = [("top_l1", ctypes.c_uint32), ("leaf_log2", ctypes.c_uint32)]
+
+
+class SSParams(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_uint32), ("l", ctypes.c_uint32), ("split", Split)]
+
+
+def fermat_ring(N: int) -> Ring:
+    return Ring(FERMAT, N, 0, 0, 0)
+
+
+def nega_ring(K: int, m: int) -> Ring:
+    return Ring(NEGA, 0, K, 0, m)
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libtft.so.  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(lib_path):
+            raise ImportError("libtft.so not built: run `python -m paper_0810_3203_amd.build` "
+                              "(or __graft_entry__.build())")
+        L = ctypes.CDLL(lib_path)
+        P, U32, U64, I = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+        RP = ctypes.POINTER(Ring)
+        L.tft_status_string.argtypes = [I]
+        L.tft_status_string.restype = ctypes.c_char_p
+        L.tft_ring_check.argtypes = [RP]
+        L.tft_ring_check.restype = I
+        L.tft_elem_bytes.argtypes = [RP]
+        L.tft_elem_bytes.restype = U64
+        L.tft_array_bytes.argtypes = [RP, U64]
+        L.tft_array_bytes.restype = U64
+        L.tft_forward.argtypes = [RP, U32, U64, U64, U64, P, P]
+        L.tft_forward.restype = I
+        L.itft_inverse.argtypes = [RP, U32, U64, U64, U64, U32, P, P]
+        L.itft_inverse.restype = I
+        L.pointwise_mul.argtypes = [RP, U64, P, P, P, U64, U32, P]
+        L.pointwise_mul.restype = I
+        L.zx_mul_ss_workspace.argtypes = [U64, U32, U64, U32, ctypes.POINTER(SSParams), ctypes.POINTER(U64)]
+        L.zx_mul_ss_workspace.restype = I
+        L.zx_mul_ss.argtypes = [P, U64, U32, P, U64, U32, P, U32, ctypes.POINTER(SSParams), P, U64, P]
+        L.zx_mul_ss.restype = I
+        L.zmx_mul_nussbaumer_workspace.argtypes = [U64, U64, U32, ctypes.POINTER(U64)]
+        L.zmx_mul_nussbaumer_workspace.restype = I
+        L.zmx_mul_nussbaumer.argtypes = [P, U64, P, U64, U64, U32, P, P, U64, P]
+        L.zmx_mul_nussbaumer.restype = I
+        L.tft_plan_create.argtypes = [RP, U32, U32, U64, U64, U64, U32, ctypes.POINTER(Split), ctypes.POINTER(P)]
+        L.tft_plan_create.restype = I
+        L.tft_plan_execute.argtypes = [P, P, P]
+        L.tft_plan_execute.restype = I
+        L.tft_plan_destroy.argtypes = [P]
+        L.tft_plan_destroy.restype = None
+        L.tft_plan_base_cases.argtypes = [P]
+        L.tft_plan_base_cases.restype = U64
+        L.tft_plan_export.argtypes = [P, P, U64, ctypes.POINTER(U64)]
+        L.tft_plan_export.restype = I
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().tft_status_string(int(status)).decode()
+
+
+def _check(rc, where):
+    if rc != 0:
+        raise TFTError(rc, where)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def ring_check(ring: Ring) -> int:
+    return lib().tft_ring_check(ctypes.byref(ring))
+
+
+def elem_bytes(ring: Ring) -> int:
+    return lib().tft_elem_bytes(ctypes.byref(ring))
+
+
+def array_bytes(ring: Ring, cells: int) -> int:
+    return lib().tft_array_bytes(ctypes.byref(ring), cells)
+
+
+def tft_forward(ring, l, s, z, n, x, stream=None):
+    """In-place TFT(2^l, theta^s, z, n) on cell array x (a device tensor of capacity 2^l)."""
+    _check(lib().tft_forward(ctypes.byref(ring), l, s, z, n, _ptr(x), _stream(stream)), "tft_forward")
+
+
+def itft_inverse(ring, l, s, z, n, f, x, stream=None):
+    """In-place ITFT(2^l, theta^s, z, n, f) on cell array x."""
+    _check(lib().itft_inverse(ctypes.byref(ring), l, s, z, n, f, _ptr(x), _stream(stream)), "itft_inverse")
+
+
+def pointwise_mul(ring, n, a, b, c, cap, scale_log2=0, stream=None):
+    """c_i = a_i b_i 2^-scale_log2 for i < n (cell arrays of capacity cap)."""
+    _check(lib().pointwise_mul(ctypes.byref(ring), n, _ptr(a), _ptr(b), _ptr(c), cap, scale_log2,
+                               _stream(stream)), "pointwise_mul")
+
+
+def zx_mul_ss_workspace(len_g, g_limbs, len_h, h_limbs, params=None) -> int:
+    out = ctypes.c_uint64(0)
+    _check(lib().zx_mul_ss_workspace(len_g, g_limbs, len_h, h_limbs, ctypes.byref(params) if params else None,
+                                     ctypes.byref(out)), "zx_mul_ss_workspace")
+    return out.value
+
+
+def zx_mul_ss(g, h, out, params=None, ws=None, stream=None):
+    """u = g h in Z[x].  g: (len_g, g_limbs) uint32-valued int32 tensor on the device, h likewise,
+    out: (len_g + len_h - 1, out_limbs).  ws: uint8 device tensor (allocated here if None)."""
+    len_g, g_limbs = g.shape
+    len_h, h_limbs = h.shape
+    out_limbs = out.shape[1]
+    need = zx_mul_ss_workspace(len_g, g_limbs, len_h, h_limbs, params)
+    if ws is None:
+        import torch
+        ws = torch.empty(need, dtype=torch.uint8, device=g.device)
+    _check(lib().zx_mul_ss(_ptr(g), len_g, g_limbs, _ptr(h), len_h, h_limbs, _ptr(out), out_limbs,
+                           ctypes.byref(params) if params else None, _ptr(ws), ws.numel() * ws.element_size(),
+                           _stream(stream)), "zx_mul_ss")
+    return out
+
+
+def zmx_mul_nussbaumer_workspace(len_g, len_h, log2K) -> int:
+    out = ctypes.c_uint64(0)
+    _check(lib().zmx_mul_nussbaumer_workspace(len_g, len_h, log2K, ctypes.byref(out)),
+           "zmx_mul_nussbaumer_workspace")
+    return out.value
+
+
+def zmx_mul_nussbaumer(g, h, m, log2K, out, ws=None, stream=None):
+    """u = g h in (Z/mZ)[x]; g, h, out are int64 device tensors holding values in [0, m)."""
+    len_g, len_h = g.numel(), h.numel()
+    need = zmx_mul_nussbaumer_workspace(len_g, len_h, log2K)
+    if ws is None:
+        import torch
+        ws = torch.empty(need, dtype=torch.uint8, device=g.device)
+    _check(lib().zmx_mul_nussbaumer(_ptr(g), len_g, _ptr(h), len_h, m, log2K, _ptr(out), _ptr(ws),
+                                    ws.numel() * ws.element_size(), _stream(stream)), "zmx_mul_nussbaumer")
+    return out
+
+
+class Plan:
+    """An explicit transform plan (tft_plan_create / execute / destroy / export)."""
+
+    def __init__(self, ring, direction, l, s, z, n, f=0, top_l1=0, leaf_log2=0):
+        self.ring = ring
+        self.l = l
+        self._p = ctypes.c_void_p()
+        sp = Split(top_l1, leaf_log2)
+        _check(lib().tft_plan_create(ctypes.byref(ring), direction, l, s, z, n, f, ctypes.byref(sp),
+                                     ctypes.byref(self._p)), "tft_plan_create")
+
+    def execute(self, x, stream=None):
+        _check(lib().tft_plan_execute(self._p, _ptr(x), _stream(stream)), "tft_plan_execute")
+
+    @property
+    def base_cases(self) -> int:
+        return lib().tft_plan_base_cases(self._p)
+
+    def export(self):
+        """The schedule as a dict of lists (see tft_plan_export in tft.h)."""
+        need = ctypes.c_uint64(0)
+        lib().tft_plan_export(self._p, None, 0, ctypes.byref(need))
+        buf = (ctypes.c_uint64 * need.value)()
+        _check(lib().tft_plan_export(self._p, buf, need.value, ctypes.byref(need)), "tft_plan_export")
+        w = list(buf)
+        npass, njob, nprog, nstep, nop, ord_, leaf = w[1:8]
+        pos = 8
+
+        def take(count, width):
+            nonlocal pos
+            out = [tuple(w[pos + i * width: pos + (i + 1) * width]) for i in range(count)]
+            pos += count * width
+            return out
+        return dict(ord=ord_, leaf_log2=leaf, passes=take(npass, 3), jobs=take(njob, 6), progs=take(nprog, 3),
+                    steps=take(nstep, 2), ops=take(nop, 5))
+
+    def close(self):
+        if self._p:
+            lib().tft_plan_destroy(self._p)
+            self._p = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,451 @@
+// C ABI of the library (include/tft.h): argument checks, plan cache, and the
+// sequencing of kernels for the transforms and the two products.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "../../include/tft.h"
+#include "kernels.hpp"
+#include "nega.hpp"
+#include "plan.hpp"
+
+using namespace tft;
+
+struct tft_plan {
+    tft_ring ring;
+    uint32_t direction, l;
+    uint64_t s, z, n;
+    uint32_t f;
+    Schedule sched;
+    std::vector<uint32_t> nwaves;  // per pass
+    void *dev = nullptr;           // device copy of jobs | progs | steps | ops
+    int dev_id = -1;
+    Job *d_jobs = nullptr;
+    LeafProg *d_progs = nullptr;
+    LeafStep *d_steps = nullptr;
+    LeafOp *d_ops = nullptr;
+    std::mutex mu;
+};
+
+namespace {
+
+bool is_pow2(uint64_t v) { return v && !(v & (v - 1)); }
+
+uint32_t log2u(uint64_t v) {
+    uint32_t l = 0;
+    while ((1ull << l) < v) l++;
+    return l;
+}
+
+int check_ring(const tft_ring *r) {
+    if (!r) return TFT_E_ARG;
+    if (r->kind == TFT_RING_FERMAT) {
+        if (r->N == 0 || r->N % 32 || r->K || r->m) return TFT_E_RING;
+        uint32_t W = r->N / 32;
+        if (!is_pow2(W) || W > 4096) return TFT_E_RING;
+        return TFT_OK;
+    }
+    if (r->kind == TFT_RING_NEGA) {
+        if (r->N || !is_pow2(r->K) || r->K < 2 || r->K > 4096) return TFT_E_RING;
+        if (r->m < 3 || !(r->m & 1) || r->m >= (1ull << 62)) return TFT_E_RING;
+        return TFT_OK;
+    }
+    return TFT_E_RING;
+}
+
+uint32_t ring_ord(const tft_ring *r) { return r->kind == TFT_RING_FERMAT ? 2u * r->N : 2u * r->K; }
+
+// LDS bytes of one cell inside a leaf workgroup
+uint64_t cell_lds_bytes(const tft_ring *r) {
+    return r->kind == TFT_RING_FERMAT ? 4ull * (r->N / 32 + 1) : 8ull * r->K;
+}
+
+uint32_t max_leaf_log2(const tft_ring *r) {
+    uint64_t cap = lds_budget_bytes() / cell_lds_bytes(r);
+    uint32_t lg = 0;
+    while ((2ull << lg) <= cap) lg++;
+    return std::min<uint32_t>(lg, 11);
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? TFT_OK : TFT_E_DEVICE; }
+
+int check_transform_args(const tft_ring *ring, uint32_t dir, uint32_t l, uint64_t z, uint64_t n, uint32_t f) {
+    int st = check_ring(ring);
+    if (st) return st;
+    if (l < 1 || l > 24) return TFT_E_ARG;
+    const uint64_t L = 1ull << l;
+    if (ring_ord(ring) % L) return TFT_E_RING;
+    if (dir == 0) {
+        if (z < 1 || z > L || n < 1 || n > L) return TFT_E_ARG;
+    } else {
+        if (f > 1 || z < 1 || z > L || z < n || n + f < 1 || n + f > L) return TFT_E_ARG;
+    }
+    return TFT_OK;
+}
+
+int plan_upload(tft_plan *p) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return TFT_E_DEVICE;
+    if (p->dev && p->dev_id == dev) return TFT_OK;
+    const Schedule &S = p->sched;
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t bj = al(S.jobs.size() * sizeof(Job)), bp = al(S.progs.size() * sizeof(LeafProg));
+    const size_t bs = al(S.steps.size() * sizeof(LeafStep)), bo = al(std::max<size_t>(1, S.ops.size()) * sizeof(LeafOp));
+    void *buf = nullptr;
+    if (hipMalloc(&buf, bj + bp + bs + bo) != hipSuccess) return TFT_E_DEVICE;
+    char *c = static_cast<char *>(buf);
+    hipError_t e = hipSuccess;
+    if (!S.jobs.empty()) e = hipMemcpy(c, S.jobs.data(), S.jobs.size() * sizeof(Job), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !S.progs.empty())
+        e = hipMemcpy(c + bj, S.progs.data(), S.progs.size() * sizeof(LeafProg), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !S.steps.empty())
+        e = hipMemcpy(c + bj + bp, S.steps.data(), S.steps.size() * sizeof(LeafStep), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !S.ops.empty())
+        e = hipMemcpy(c + bj + bp + bs, S.ops.data(), S.ops.size() * sizeof(LeafOp), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(buf);
+        return TFT_E_DEVICE;
+    }
+    if (p->dev) (void)hipFree(p->dev);
+    p->dev = buf;
+    p->dev_id = dev;
+    p->d_jobs = reinterpret_cast<Job *>(c);
+    p->d_progs = reinterpret_cast<LeafProg *>(c + bj);
+    p->d_steps = reinterpret_cast<LeafStep *>(c + bj + bp);
+    p->d_ops = reinterpret_cast<LeafOp *>(c + bj + bp + bs);
+    return TFT_OK;
+}
+
+tft_plan *plan_build(const tft_ring *ring, uint32_t dir, uint32_t l, uint64_t s, uint64_t z, uint64_t n, uint32_t f,
+                     const tft_split *split) {
+    tft_plan *p = new tft_plan();
+    p->ring = *ring;
+    p->direction = dir;
+    p->l = l;
+    p->s = s % ring_ord(ring);
+    p->z = z;
+    p->n = n;
+    p->f = dir ? f : 0;
+    uint32_t leaf = max_leaf_log2(ring);
+    if (split && split->leaf_log2) leaf = std::min(leaf, std::max<uint32_t>(1, split->leaf_log2));
+    uint32_t top = (split && split->top_l1 && split->top_l1 < l) ? split->top_l1 : 0;
+    p->sched = build_schedule(dir, l, ring_ord(ring), p->s, z, n, p->f, leaf, top);
+    const uint32_t seg = ring->kind == TFT_RING_FERMAT ? std::min<uint32_t>(ring->N / 32, 64) : 64;
+    const uint32_t G = 64 / seg;
+    for (const PassDesc &pd : p->sched.passes) {
+        uint32_t w = (pd.max_ops + G - 1) / G;
+        p->nwaves.push_back(std::min<uint32_t>(8, std::max<uint32_t>(1, w)));
+    }
+    return p;
+}
+
+int plan_run(tft_plan *p, void *x, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    int rc = plan_upload(p);
+    if (rc) return rc;
+    const uint64_t cap = 1ull << p->l;
+    const uint32_t ord_mask = ring_ord(&p->ring) - 1;
+    for (size_t i = 0; i < p->sched.passes.size(); i++) {
+        const PassDesc &pd = p->sched.passes[i];
+        hipError_t e;
+        if (p->ring.kind == TFT_RING_FERMAT)
+            e = launch_fermat_leaf(p->ring.N / 32, p->nwaves[i], pd.job_count, pd.max_len, p->d_jobs, pd.job_begin,
+                                   p->d_progs, p->d_steps, p->d_ops, static_cast<uint32_t *>(x), cap, ord_mask, st);
+        else
+            e = launch_nega_leaf(p->ring.K, p->ring.m, p->nwaves[i], pd.job_count, pd.max_len, p->d_jobs,
+                                 pd.job_begin, p->d_progs, p->d_steps, p->d_ops, static_cast<uint64_t *>(x), ord_mask,
+                                 st);
+        if (e != hipSuccess) return TFT_E_DEVICE;
+    }
+    return TFT_OK;
+}
+
+// cache of plans used by the one-call entry points
+std::mutex g_cache_mu;
+std::map<std::vector<uint64_t>, tft_plan *> g_cache;
+
+tft_plan *cached_plan(const tft_ring *ring, uint32_t dir, uint32_t l, uint64_t s, uint64_t z, uint64_t n, uint32_t f,
+                      const tft_split *split) {
+    std::vector<uint64_t> key{ring->kind, ring->N, ring->K, ring->m, dir, l, s % ring_ord(ring), z, n, dir ? f : 0,
+                              split ? split->top_l1 : 0, split ? split->leaf_log2 : 0};
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) return it->second;
+    tft_plan *p = plan_build(ring, dir, l, s, z, n, f, split);
+    g_cache[key] = p;
+    return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tft_status_string(int status) {
+    switch (status) {
+        case TFT_OK: return "ok";
+        case TFT_E_ARG: return "invalid argument";
+        case TFT_E_RING: return "unsupported ring or no root of the needed order";
+        case TFT_E_RANGE: return "output does not fit";
+        case TFT_E_WORKSPACE: return "workspace missing or too small";
+        case TFT_E_DEVICE: return "HIP device error";
+        case TFT_E_UNSUPPORTED: return "not supported by this build";
+        default: return "unknown status";
+    }
+}
+
+int tft_ring_check(const tft_ring *ring) { return check_ring(ring); }
+
+uint64_t tft_elem_bytes(const tft_ring *ring) {
+    if (check_ring(ring)) return 0;
+    return ring->kind == TFT_RING_FERMAT ? 4ull * (ring->N / 32 + 1) : 8ull * ring->K;
+}
+
+uint64_t tft_array_bytes(const tft_ring *ring, uint64_t cells) { return tft_elem_bytes(ring) * cells; }
+
+int tft_plan_create(const tft_ring *ring, uint32_t direction, uint32_t l, uint64_t s, uint64_t z, uint64_t n,
+                    uint32_t f, const tft_split *split, tft_plan **plan) {
+    if (!plan || direction > 1) return TFT_E_ARG;
+    int st = check_transform_args(ring, direction, l, z, n, f);
+    if (st) return st;
+    if (split && split->top_l1 && split->top_l1 >= l) return TFT_E_ARG;
+    *plan = plan_build(ring, direction, l, s, z, n, f, split);
+    return TFT_OK;
+}
+
+int tft_plan_execute(tft_plan *plan, void *x, void *stream) {
+    if (!plan || !x) return TFT_E_ARG;
+    return plan_run(plan, x, static_cast<hipStream_t>(stream));
+}
+
+void tft_plan_destroy(tft_plan *plan) {
+    if (!plan) return;
+    if (plan->dev) (void)hipFree(plan->dev);
+    delete plan;
+}
+
+uint64_t tft_plan_base_cases(const tft_plan *plan) { return plan ? plan->sched.base_cases : 0; }
+
+int tft_plan_export(const tft_plan *plan, uint64_t *buf, uint64_t cap_words, uint64_t *needed) {
+    if (!plan || !needed) return TFT_E_ARG;
+    const Schedule &S = plan->sched;
+    uint64_t words = 8 + 3 * S.passes.size() + 6 * S.jobs.size() + 3 * S.progs.size() + 2 * S.steps.size() +
+                     5 * S.ops.size();
+    *needed = words;
+    if (!buf || cap_words < words) return TFT_E_ARG;
+    uint64_t *w = buf;
+    *w++ = 1;
+    *w++ = S.passes.size();
+    *w++ = S.jobs.size();
+    *w++ = S.progs.size();
+    *w++ = S.steps.size();
+    *w++ = S.ops.size();
+    *w++ = S.ord;
+    *w++ = S.leaf_log2;
+    for (const PassDesc &p : S.passes) {
+        *w++ = p.job_begin;
+        *w++ = p.job_count;
+        *w++ = p.max_len;
+    }
+    for (const Job &j : S.jobs) {
+        *w++ = j.base;
+        *w++ = j.stride;
+        *w++ = j.prog;
+        *w++ = j.s;
+        *w++ = j.nload;
+        *w++ = j.nstore;
+    }
+    for (const LeafProg &p : S.progs) {
+        *w++ = p.step_begin;
+        *w++ = p.step_count;
+        *w++ = p.len;
+    }
+    for (const LeafStep &s : S.steps) {
+        *w++ = s.op_begin;
+        *w++ = s.op_count;
+    }
+    for (const LeafOp &o : S.ops) {
+        *w++ = o.w0 & 15u;
+        *w++ = (o.w0 >> 4) & 16383u;
+        *w++ = (o.w0 >> 18) & 16383u;
+        *w++ = o.w1 >> 24;
+        *w++ = o.w1 & 0xFFFFFFu;
+    }
+    return TFT_OK;
+}
+
+int tft_forward(const tft_ring *ring, uint32_t l, uint64_t s, uint64_t z, uint64_t n, void *x, void *stream) {
+    int st = check_transform_args(ring, 0, l, z, n, 0);
+    if (st) return st;
+    if (!x) return TFT_E_ARG;
+    return plan_run(cached_plan(ring, 0, l, s, z, n, 0, nullptr), x, static_cast<hipStream_t>(stream));
+}
+
+int itft_inverse(const tft_ring *ring, uint32_t l, uint64_t s, uint64_t z, uint64_t n, uint32_t f, void *x,
+                 void *stream) {
+    int st = check_transform_args(ring, 1, l, z, n, f);
+    if (st) return st;
+    if (!x) return TFT_E_ARG;
+    return plan_run(cached_plan(ring, 1, l, s, z, n, f, nullptr), x, static_cast<hipStream_t>(stream));
+}
+
+int pointwise_mul(const tft_ring *ring, uint64_t n, const void *a, const void *b, void *c, uint64_t cap,
+                  uint32_t scale_log2, void *stream) {
+    int st = check_ring(ring);
+    if (st) return st;
+    if (!a || !b || !c || n > cap || n > 0xFFFFFFFFull) return TFT_E_ARG;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const uint32_t ord = ring_ord(ring);
+    if (ring->kind == TFT_RING_FERMAT) {
+        const uint32_t e = (uint32_t)((ord - (scale_log2 % ord)) % ord);
+        return hip_status(launch_fermat_pointwise(ring->N / 32, n, static_cast<const uint32_t *>(a),
+                                                  static_cast<const uint32_t *>(b), static_cast<uint32_t *>(c), cap,
+                                                  e, hs));
+    }
+    return hip_status(launch_nega_pointwise(ring->K, ring->m, n, static_cast<const uint64_t *>(a),
+                                            static_cast<const uint64_t *>(b), static_cast<uint64_t *>(c),
+                                            scale_log2, hs));
+}
+
+// ---------------------------------------------------------------------------
+// Schoenhage-Strassen in Z[x] (Sect. 5.1)
+// ---------------------------------------------------------------------------
+
+struct SSShape {
+    uint32_t N, W, l;
+    uint64_t n, L, ws;
+};
+
+static int ss_shape(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h_limbs, const tft_ss_params *p,
+                    SSShape *o) {
+    if (len_g < 1 || len_h < 1 || g_limbs < 1 || h_limbs < 1) return TFT_E_ARG;
+    const uint64_t n = len_g + len_h - 1;
+    const uint64_t bits = 32ull * (g_limbs + h_limbs) + log2u(std::min(len_g, len_h));
+    uint32_t l = p && p->l ? p->l : std::max<uint32_t>(1, log2u(n));
+    if (l > 24 || (1ull << l) < n) return TFT_E_ARG;
+    const uint64_t L = 1ull << l;
+    uint64_t N;
+    if (p && p->N) {
+        N = p->N;
+        if (N % 32 || !is_pow2(N / 32) || N / 32 > 4096) return TFT_E_RING;
+        if ((2 * N) % L) return TFT_E_RING;
+        if (N < bits) return TFT_E_RANGE;
+    } else {
+        uint64_t W = 1;
+        while (32 * W < bits || 64 * W < L) W <<= 1;
+        if (W > 4096) return TFT_E_UNSUPPORTED;
+        N = 32 * W;
+    }
+    o->N = (uint32_t)N;
+    o->W = (uint32_t)(N / 32);
+    o->l = l;
+    o->n = n;
+    o->L = L;
+    o->ws = 2 * L * (o->W + 1) * 4ull;
+    return TFT_OK;
+}
+
+int zx_mul_ss_workspace(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h_limbs,
+                        const tft_ss_params *params, uint64_t *bytes) {
+    if (!bytes) return TFT_E_ARG;
+    SSShape sh;
+    int st = ss_shape(len_g, g_limbs, len_h, h_limbs, params, &sh);
+    if (st) return st;
+    *bytes = sh.ws;
+    return TFT_OK;
+}
+
+int zx_mul_ss(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uint32_t *h, uint64_t len_h,
+              uint32_t h_limbs, uint32_t *out, uint32_t out_limbs, const tft_ss_params *params, void *ws,
+              uint64_t ws_bytes, void *stream) {
+    if (!g || !h || !out) return TFT_E_ARG;
+    SSShape sh;
+    int st = ss_shape(len_g, g_limbs, len_h, h_limbs, params, &sh);
+    if (st) return st;
+    const uint64_t bits = 32ull * (g_limbs + h_limbs) + log2u(std::min(len_g, len_h));
+    if (32ull * out_limbs < bits) return TFT_E_RANGE;
+    if (!ws || ws_bytes < sh.ws) return TFT_E_WORKSPACE;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    tft_ring ring{TFT_RING_FERMAT, sh.N, 0, 0, 0};
+    uint32_t *A = static_cast<uint32_t *>(ws);
+    uint32_t *B = A + sh.L * (sh.W + 1);
+    const tft_split *split = params ? &params->split : nullptr;
+    hipError_t e = launch_fermat_pack(sh.W, g, len_g, g_limbs, A, sh.L, hs);
+    if (e == hipSuccess) e = launch_fermat_pack(sh.W, h, len_h, h_limbs, B, sh.L, hs);
+    if (e != hipSuccess) return TFT_E_DEVICE;
+    st = plan_run(cached_plan(&ring, 0, sh.l, 0, len_g, sh.n, 0, split), A, hs);
+    if (st) return st;
+    st = plan_run(cached_plan(&ring, 0, sh.l, 0, len_h, sh.n, 0, split), B, hs);
+    if (st) return st;
+    e = launch_fermat_pointwise(sh.W, sh.n, A, B, A, sh.L, (uint32_t)((2 * sh.N - sh.l) % (2 * sh.N)), hs);
+    if (e != hipSuccess) return TFT_E_DEVICE;
+    st = plan_run(cached_plan(&ring, 1, sh.l, 0, sh.n, sh.n, 0, split), A, hs);
+    if (st) return st;
+    return hip_status(launch_fermat_unpack(sh.W, A, sh.L, sh.n, out, out_limbs, hs));
+}
+
+// ---------------------------------------------------------------------------
+// Schoenhage-Nussbaumer in (Z/mZ)[x] (Sect. 5.2)
+// ---------------------------------------------------------------------------
+
+struct SNShape {
+    uint32_t K, l;
+    uint64_t zg, zh, n, L, ws;
+};
+
+static int sn_shape(uint64_t len_g, uint64_t len_h, uint32_t log2K, SNShape *o) {
+    if (len_g < 1 || len_h < 1 || log2K < 1 || log2K > 12) return TFT_E_ARG;
+    const uint64_t K = 1ull << log2K, piece = K / 2;
+    o->K = (uint32_t)K;
+    o->zg = (len_g + piece - 1) / piece;
+    o->zh = (len_h + piece - 1) / piece;
+    o->n = o->zg + o->zh - 1;
+    o->l = std::max<uint32_t>(1, log2u(o->n));
+    o->L = 1ull << o->l;
+    if (o->L > 2 * K) return TFT_E_ARG;
+    o->ws = 2 * o->L * K * 8ull;
+    return TFT_OK;
+}
+
+int zmx_mul_nussbaumer_workspace(uint64_t len_g, uint64_t len_h, uint32_t log2K, uint64_t *bytes) {
+    if (!bytes) return TFT_E_ARG;
+    SNShape sh;
+    int st = sn_shape(len_g, len_h, log2K, &sh);
+    if (st) return st;
+    *bytes = sh.ws;
+    return TFT_OK;
+}
+
+int zmx_mul_nussbaumer(const uint64_t *g, uint64_t len_g, const uint64_t *h, uint64_t len_h, uint64_t m,
+                       uint32_t log2K, uint64_t *out, void *ws, uint64_t ws_bytes, void *stream) {
+    if (!g || !h || !out) return TFT_E_ARG;
+    SNShape sh;
+    int st = sn_shape(len_g, len_h, log2K, &sh);
+    if (st) return st;
+    tft_ring ring{TFT_RING_NEGA, 0, sh.K, 0, m};
+    st = check_ring(&ring);
+    if (st) return st;
+    if (!ws || ws_bytes < sh.ws) return TFT_E_WORKSPACE;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    uint64_t *A = static_cast<uint64_t *>(ws);
+    uint64_t *B = A + sh.L * sh.K;
+    hipError_t e = launch_nega_pack(sh.K, g, len_g, A, sh.zg, hs);
+    if (e == hipSuccess) e = launch_nega_pack(sh.K, h, len_h, B, sh.zh, hs);
+    if (e != hipSuccess) return TFT_E_DEVICE;
+    st = plan_run(cached_plan(&ring, 0, sh.l, 0, sh.zg, sh.n, 0, nullptr), A, hs);
+    if (st) return st;
+    st = plan_run(cached_plan(&ring, 0, sh.l, 0, sh.zh, sh.n, 0, nullptr), B, hs);
+    if (st) return st;
+    e = launch_nega_pointwise(sh.K, m, sh.n, A, B, A, sh.l, hs);
+    if (e != hipSuccess) return TFT_E_DEVICE;
+    st = plan_run(cached_plan(&ring, 1, sh.l, 0, sh.n, sh.n, 0, nullptr), A, hs);
+    if (st) return st;
+    return hip_status(launch_nega_unpack(sh.K, m, A, sh.n, out, len_g + len_h - 1, hs));
+}
+
+}  // extern "C"

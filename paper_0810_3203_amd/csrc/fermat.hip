@@ -1,0 +1,387 @@
+// HIP kernels for R = Z/(2^N+1) on gfx950: the leaf executor of the
+// cache-friendly TFT/ITFT (Alg. 1, Alg. 2), the pointwise products of Sect. 2,
+// and the packing of Z[x] coefficients into R (Sect. 5.1).
+#include <hip/hip_runtime.h>
+
+#include "desc.hpp"
+#include "fermat_dev.hpp"
+#include "kernels.hpp"
+
+namespace tft {
+
+namespace {
+
+constexpr uint32_t kLdsBudget = 160u * 1024u;
+
+// Copy leaf cells [0, n) between the global array and LDS.
+template <int W, bool IN>
+__device__ __forceinline__ void copy_cells(uint32_t *sm, uint32_t *x, const Job &J, uint32_t n, uint32_t tid,
+                                           uint32_t nthr) {
+    if constexpr (W % 4 == 0) {
+        constexpr uint32_t WQ = W / 4;
+        const uint32_t total = n * WQ;
+        for (uint32_t q = tid; q < total; q += nthr) {
+            const uint32_t cell = q / WQ, off = q % WQ;
+            uint4 *g = reinterpret_cast<uint4 *>(x + (J.base + (uint64_t)cell * J.stride) * W) + off;
+            uint4 *s = reinterpret_cast<uint4 *>(sm) + q;
+            if (IN)
+                *s = *g;
+            else
+                *g = *s;
+        }
+    } else {
+        const uint32_t total = n * W;
+        for (uint32_t q = tid; q < total; q += nthr) {
+            const uint32_t cell = q / W, off = q % W;
+            uint32_t *g = x + (J.base + (uint64_t)cell * J.stride) * W + off;
+            if (IN)
+                sm[q] = *g;
+            else
+                *g = sm[q];
+        }
+    }
+}
+
+template <int S, int R>
+__global__ void __launch_bounds__(512) fermat_leaf_kernel(const Job *__restrict__ jobs,
+                                                           const LeafProg *__restrict__ progs,
+                                                           const LeafStep *__restrict__ steps,
+                                                           const LeafOp *__restrict__ ops, uint32_t *__restrict__ x,
+                                                           uint64_t cap, uint32_t ord_mask, uint32_t lds_cells,
+                                                           uint32_t job_offset) {
+    using F = FermatSeg<S, R>;
+    constexpr int W = S * R;
+    constexpr uint32_t G = 64 / S;
+    extern __shared__ uint32_t sm[];
+    uint32_t *stop = sm + (size_t)lds_cells * W;
+    const Job J = jobs[job_offset + blockIdx.x];
+    const LeafProg P = progs[J.prog];
+    const uint32_t tid = threadIdx.x, nthr = blockDim.x;
+
+    copy_cells<W, true>(sm, x, J, J.nload, tid, nthr);
+    for (uint32_t t = tid; t < J.nload; t += nthr) stop[t] = x[cap * W + J.base + (uint64_t)t * J.stride];
+    __syncthreads();
+
+    const FermatOps<F> B;
+    const uint32_t wave = tid >> 6, nwaves = nthr >> 6;
+    const uint32_t g = B.lane / S;
+    for (uint32_t st = 0; st < P.step_count; ++st) {
+        const LeafStep LS = steps[P.step_begin + st];
+        for (uint32_t jb = wave * G; jb < LS.op_count; jb += nwaves * G) {
+            const uint32_t j = jb + g;
+            if (j < LS.op_count) {
+                const LeafOp o = ops[LS.op_begin + j];
+                const uint32_t code = o.w0 & 15u;
+                const uint32_t i0 = (o.w0 >> 4) & 16383u, i1 = (o.w0 >> 18) & 16383u;
+                const uint32_t e =
+                    (uint32_t)((((uint64_t)J.s << (o.w1 >> 24)) + (uint64_t)(o.w1 & 0xFFFFFFu)) & ord_mask);
+                uint32_t *x0 = sm + i0 * W, *x1 = sm + i1 * W;
+                uint32_t *t0 = stop + i0, *t1 = stop + i1;
+                switch (code) {
+                    case OP_T22: B.t22(x0, x1, t0, t1, e); break;
+                    case OP_T21: B.t21(x0, x1, t0, t1, e); break;
+                    case OP_T12: B.add2(x0, x1, t0, t1); break;
+                    case OP_I2: B.i2(x0, x1, t0, t1, (0u - e) & ord_mask); break;
+                    case OP_I1F1Z2: B.i1f1(x0, x1, t0, t1, e, true); break;
+                    case OP_I1F1Z1: B.i1f1(x0, x1, t0, t1, e, false); break;
+                    case OP_I1F0Z2: B.dbl_sub(x0, x1, t0, t1); break;
+                    case OP_I1F0Z1: B.dbl_sub(x0, nullptr, t0, nullptr); break;
+                    case OP_I0Z2:
+                        B.add2(x0, x1, t0, t1);
+                        B.scale(x0, t0, ord_mask);  // 2^(2N-1) = 1/2
+                        break;
+                    case OP_I0Z1: B.scale(x0, t0, ord_mask); break;
+                    default: break;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    copy_cells<W, false>(sm, x, J, J.nstore, tid, nthr);
+    for (uint32_t t = tid; t < J.nstore; t += nthr) x[cap * W + J.base + (uint64_t)t * J.stride] = stop[t];
+}
+
+// ---------------------------------------------------------------------------
+// pointwise products  c = a b 2^scale_e  in Z/(2^N+1)
+//
+// One workgroup per product.  The negacyclic limb convolution
+//   d_k = sum_{i+j=k} a_i b_j - sum_{i+j=k+W} a_i b_j     (2^N = -1)
+// is accumulated per output column in 96-bit sums (P_k, N_k), each thread
+// owning 8 consecutive columns and sliding a register window over b.  The
+// column sums are then folded into four limb vectors PL + HP - NL - HN that
+// one wave adds with the carry-lookahead chains, followed by canonicalisation
+// and the multiplication by 2^scale_e.
+// ---------------------------------------------------------------------------
+
+constexpr int PW_COLS = 8;
+
+// threads of a pointwise workgroup for W limbs: one per PW_COLS columns, 64..256
+constexpr uint32_t pw_threads(int W) {
+    uint32_t t = (uint32_t)W / PW_COLS;
+    t = t < 64 ? 64 : (t > 256 ? 256 : t);
+    return (t + 63) / 64 * 64;
+}
+
+template <int S, int R>
+__global__ void __launch_bounds__(256) fermat_pointwise_kernel(const uint32_t *__restrict__ a,
+                                                               const uint32_t *__restrict__ b, uint32_t *c,
+                                                               uint64_t cap, uint32_t scale_e) {
+    using F = FermatSeg<S, R>;
+    constexpr int W = S * R;
+    extern __shared__ uint32_t sm[];
+    uint32_t *A = sm, *Bv = A + W;
+    uint32_t *P0 = Bv + W, *P1 = P0 + W, *P2 = P1 + W, *N0 = P2 + W, *N1 = N0 + W, *N2 = N1 + W;
+    uint32_t *Y = N2 + W;
+    __shared__ uint32_t topY;
+    const uint64_t i = blockIdx.x;
+    const uint32_t tid = threadIdx.x, nthr = blockDim.x;
+
+    for (uint32_t q = tid; q < (uint32_t)W; q += nthr) {
+        A[q] = a[i * W + q];
+        Bv[q] = b[i * W + q];
+    }
+    const uint32_t ta = a[cap * W + i], tb = b[cap * W + i];
+    __syncthreads();
+
+    const bool special = (ta | tb) != 0u;
+    if (!special) {
+        // column sums, PW_COLS consecutive columns per thread
+        for (uint32_t k0 = tid * PW_COLS; k0 < (uint32_t)W; k0 += nthr * PW_COLS) {
+            constexpr int NC = (W < PW_COLS) ? W : PW_COLS;
+            uint64_t pl[NC], nl[NC];
+            uint32_t ph[NC], nh[NC], bw[NC];
+#pragma unroll
+            for (int cc = 0; cc < NC; ++cc) {
+                pl[cc] = nl[cc] = 0;
+                ph[cc] = nh[cc] = 0;
+                bw[cc] = Bv[(k0 + cc) & (W - 1)];  // window at i = 0: b_{k0+cc}
+            }
+            for (uint32_t ii = 0; ii < (uint32_t)W; ++ii) {
+                const uint64_t av = A[ii];
+#pragma unroll
+                for (int cc = 0; cc < NC; ++cc) {
+                    const uint64_t pr = av * bw[cc];
+                    if (ii <= k0 + cc) {
+                        const uint64_t s = pl[cc] + pr;
+                        ph[cc] += s < pr ? 1u : 0u;
+                        pl[cc] = s;
+                    } else {
+                        const uint64_t s = nl[cc] + pr;
+                        nh[cc] += s < pr ? 1u : 0u;
+                        nl[cc] = s;
+                    }
+                }
+                // slide: next i needs b_{k0+cc-(i+1)}
+#pragma unroll
+                for (int cc = NC - 1; cc > 0; --cc) bw[cc] = bw[cc - 1];
+                bw[0] = Bv[(k0 - ii - 1u) & (W - 1)];
+            }
+#pragma unroll
+            for (int cc = 0; cc < NC; ++cc) {
+                const uint32_t k = k0 + cc;
+                P0[k] = (uint32_t)pl[cc];
+                P1[k] = (uint32_t)(pl[cc] >> 32);
+                P2[k] = ph[cc];
+                N0[k] = (uint32_t)nl[cc];
+                N1[k] = (uint32_t)(nl[cc] >> 32);
+                N2[k] = nh[cc];
+            }
+        }
+        __syncthreads();
+        // fold words of weight 2^(32(k+w)) onto limb positions (2^N = -1)
+        constexpr uint32_t T = pw_threads(W);
+        constexpr int NS = (W + (int)T - 1) / (int)T;
+        uint64_t posv[NS], negv[NS];
+#pragma unroll
+        for (int sl = 0; sl < NS; ++sl) {
+            const uint32_t j = tid + (uint32_t)sl * T;
+            uint64_t pos = 0, neg = 0;
+            if (j < (uint32_t)W) {
+#pragma unroll
+                for (uint32_t w = 0; w < 3; ++w) {
+                    const uint32_t k = (j + 3u * W - w) % (uint32_t)W;
+                    const uint32_t wraps = (k + w) / (uint32_t)W;
+                    const uint32_t pw = w == 0 ? P0[k] : (w == 1 ? P1[k] : P2[k]);
+                    const uint32_t nw = w == 0 ? N0[k] : (w == 1 ? N1[k] : N2[k]);
+                    if (wraps & 1u) {
+                        pos += nw;
+                        neg += pw;
+                    } else {
+                        pos += pw;
+                        neg += nw;
+                    }
+                }
+            }
+            posv[sl] = pos;
+            negv[sl] = neg;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int sl = 0; sl < NS; ++sl) {
+            const uint32_t j = tid + (uint32_t)sl * T;
+            if (j < (uint32_t)W) {
+                A[j] = (uint32_t)posv[sl];           // PL
+                Bv[j] = (uint32_t)negv[sl];          // NL
+                P0[j] = (uint32_t)(posv[sl] >> 32);  // PHI (lands at j+1)
+                N0[j] = (uint32_t)(negv[sl] >> 32);  // NHI (lands at j+1)
+            }
+        }
+        __syncthreads();
+    }
+
+    if (tid < 64) {
+        const FermatOps<F> Bo;
+        const bool active = (Bo.lane < (uint32_t)S);  // segment 0 only
+        if (active) {
+            if (!special) {
+                uint64_t c1 = 0, c2 = 0, c3 = 0;
+                for (int r = 0; r < R; ++r) {
+                    const uint32_t k = (uint32_t)r * S + Bo.l;
+                    const uint32_t hp = k ? P0[k - 1] : N0[W - 1];
+                    const uint32_t hn = k ? N0[k - 1] : P0[W - 1];
+                    uint32_t v = Bo.add_row(A[k], hp, c1);
+                    v = Bo.sub_row(v, Bv[k], c2);
+                    v = Bo.sub_row(v, hn, c3);
+                    Y[k] = v;
+                }
+                Bo.canon(Y, &topY, (int)Bo.seg_bit(c1) - (int)Bo.seg_bit(c2) - (int)Bo.seg_bit(c3), 0, 0u);
+            } else if (ta && tb) {
+                // (-1)(-1) = 1
+                for (int r = 0; r < R; ++r) Y[(uint32_t)r * S + Bo.l] = 0u;
+                Bo.canon(Y, &topY, -1, 0, 0u);
+            } else {
+                // (-1) * v = 2^N + 1 - v = ~v + 2
+                const uint32_t *v = ta ? Bv : A;
+                for (int r = 0; r < R; ++r) {
+                    const uint32_t k = (uint32_t)r * S + Bo.l;
+                    Y[k] = ~v[k];
+                }
+                Bo.canon(Y, &topY, -2, 0, 0u);
+            }
+            if (scale_e) Bo.scale(Y, &topY, scale_e);
+        }
+    }
+    __syncthreads();
+    for (uint32_t q = tid; q < (uint32_t)W; q += nthr) c[i * W + q] = Y[q];
+    if (tid == 0) c[cap * W + i] = topY;
+}
+
+__global__ void fermat_pack_kernel(const uint32_t *__restrict__ coef, uint64_t count, uint32_t climbs,
+                                   uint32_t *__restrict__ x, uint64_t cap, uint32_t W) {
+    const uint64_t total = count * (uint64_t)W;
+    for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < total;
+         q += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t cell = q / W;
+        const uint32_t t = (uint32_t)(q % W);
+        x[q] = t < climbs ? coef[cell * climbs + t] : 0u;
+        if (t == 0) x[cap * W + cell] = 0u;
+    }
+}
+
+__global__ void fermat_unpack_kernel(const uint32_t *__restrict__ x, uint64_t cap, uint64_t count,
+                                     uint32_t *__restrict__ out, uint32_t olimbs, uint32_t W) {
+    const uint64_t total = count * (uint64_t)olimbs;
+    for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < total;
+         q += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t cell = q / olimbs;
+        const uint32_t t = (uint32_t)(q % olimbs);
+        out[q] = t < W ? x[cell * W + t] : (t == W ? x[cap * W + cell] : 0u);
+    }
+}
+
+template <int S, int R>
+hipError_t leaf_launch(uint32_t nwaves, uint32_t njobs, uint32_t lds_cells, const Job *jobs, uint32_t job_offset,
+                       const LeafProg *progs, const LeafStep *steps, const LeafOp *ops, uint32_t *x, uint64_t cap,
+                       uint32_t ord_mask, hipStream_t st) {
+    constexpr int W = S * R;
+    const size_t lds = (size_t)lds_cells * (W + 1) * 4;
+    if (lds > kLdsBudget) return hipErrorInvalidValue;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fermat_leaf_kernel<S, R>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL((fermat_leaf_kernel<S, R>), dim3(njobs), dim3(64 * nwaves), lds, st, jobs, progs, steps, ops,
+                       x, cap, ord_mask, lds_cells, job_offset);
+    return hipGetLastError();
+}
+
+template <int S, int R>
+hipError_t pointwise_launch(uint64_t n, const uint32_t *a, const uint32_t *b, uint32_t *c, uint64_t cap,
+                            uint32_t scale_e, hipStream_t st) {
+    constexpr int W = S * R;
+    const size_t lds = (size_t)9 * W * 4;
+    if (lds > kLdsBudget) return hipErrorInvalidValue;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fermat_pointwise_kernel<S, R>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const uint32_t thr = pw_threads(W);
+    hipLaunchKernelGGL((fermat_pointwise_kernel<S, R>), dim3((uint32_t)n), dim3(thr), lds, st, a, b, c, cap,
+                       scale_e);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+uint32_t lds_budget_bytes() { return kLdsBudget; }
+
+#define TFT_FERMAT_DISPATCH(W, FN, ...)                      \
+    switch (W) {                                             \
+        case 1: return FN<1, 1>(__VA_ARGS__);                \
+        case 2: return FN<2, 1>(__VA_ARGS__);                \
+        case 4: return FN<4, 1>(__VA_ARGS__);                \
+        case 8: return FN<8, 1>(__VA_ARGS__);                \
+        case 16: return FN<16, 1>(__VA_ARGS__);              \
+        case 32: return FN<32, 1>(__VA_ARGS__);              \
+        case 64: return FN<64, 1>(__VA_ARGS__);              \
+        case 128: return FN<64, 2>(__VA_ARGS__);             \
+        case 256: return FN<64, 4>(__VA_ARGS__);             \
+        case 512: return FN<64, 8>(__VA_ARGS__);             \
+        case 1024: return FN<64, 16>(__VA_ARGS__);           \
+        case 2048: return FN<64, 32>(__VA_ARGS__);           \
+        case 4096: return FN<64, 64>(__VA_ARGS__);           \
+        default: return hipErrorInvalidValue;                \
+    }
+
+hipError_t launch_fermat_leaf(uint32_t W, uint32_t nwaves, uint32_t njobs, uint32_t lds_cells, const Job *jobs,
+                              uint32_t job_offset, const LeafProg *progs, const LeafStep *steps, const LeafOp *ops,
+                              uint32_t *x, uint64_t cap, uint32_t ord_mask, hipStream_t st) {
+    if (njobs == 0) return hipSuccess;
+    TFT_FERMAT_DISPATCH(W, leaf_launch, nwaves, njobs, lds_cells, jobs, job_offset, progs, steps, ops, x, cap,
+                        ord_mask, st)
+}
+
+hipError_t launch_fermat_pointwise(uint32_t W, uint64_t n, const uint32_t *a, const uint32_t *b, uint32_t *c,
+                                   uint64_t cap, uint32_t scale_e, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    TFT_FERMAT_DISPATCH(W, pointwise_launch, n, a, b, c, cap, scale_e, st)
+}
+
+hipError_t launch_fermat_pack(uint32_t W, const uint32_t *coef, uint64_t count, uint32_t climbs, uint32_t *x,
+                              uint64_t cap, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    const uint64_t total = count * W;
+    uint32_t blocks = (uint32_t)((total + 255) / 256);
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(fermat_pack_kernel, dim3(blocks), dim3(256), 0, st, coef, count, climbs, x, cap, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_fermat_unpack(uint32_t W, const uint32_t *x, uint64_t cap, uint64_t count, uint32_t *out,
+                                uint32_t olimbs, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    const uint64_t total = count * olimbs;
+    uint32_t blocks = (uint32_t)((total + 255) / 256);
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(fermat_unpack_kernel, dim3(blocks), dim3(256), 0, st, x, cap, count, out, olimbs, W);
+    return hipGetLastError();
+}
+
+}  // namespace tft

@@ -1,0 +1,384 @@
+// HIP kernels for R = (Z/mZ)[y]/(y^K+1), theta = y of order 2K (Sect. 5.2):
+// leaf executor of the cache-friendly TFT/ITFT, negacyclic pointwise products,
+// and the cutting of (Z/mZ)[x] operands into pieces of K/2 coefficients.
+//
+// An element is K coefficients in [0, m), m odd < 2^62.  Multiplication by
+// y^e is an index rotation with a sign flip of the coefficients that pass
+// y^K = -1; the ring needs no carries, so a coefficient is independent work.
+#include <hip/hip_runtime.h>
+
+#include "desc.hpp"
+#include "nega.hpp"
+
+namespace tft {
+
+namespace {
+
+constexpr uint32_t kLdsBudget = 160u * 1024u;
+
+__device__ __forceinline__ uint64_t madd(uint64_t a, uint64_t b, uint64_t m) {
+    const uint64_t s = a + b;
+    return s >= m ? s - m : s;
+}
+__device__ __forceinline__ uint64_t msub(uint64_t a, uint64_t b, uint64_t m) { return a >= b ? a - b : a + m - b; }
+__device__ __forceinline__ uint64_t mneg(uint64_t a, uint64_t m) { return a ? m - a : 0; }
+__device__ __forceinline__ uint64_t mhalf(uint64_t a, uint64_t m) { return (a & 1) ? (a + m) >> 1 : a >> 1; }
+
+template <int S_, int R_>
+struct NegaSeg {
+    static constexpr int S = S_;
+    static constexpr int R = R_;
+    static constexpr int K = S * R;
+    uint32_t l;
+    uint64_t m;
+
+    // coefficient k of y^e * x  (0 <= e < 2K)
+    __device__ __forceinline__ uint64_t rot(const uint64_t *x, uint32_t k, uint32_t e) const {
+        const uint32_t t = (k - e) & (2u * K - 1u);
+        const uint64_t v = x[t & (K - 1u)];
+        return (t & (uint32_t)K) ? mneg(v, m) : v;
+    }
+    __device__ __forceinline__ uint64_t rot_diff(const uint64_t *x0, const uint64_t *x1, uint32_t k,
+                                                 uint32_t e) const {
+        const uint32_t t = (k - e) & (2u * K - 1u);
+        const uint32_t src = t & (K - 1u);
+        return (t & (uint32_t)K) ? msub(x1[src], x0[src], m) : msub(x0[src], x1[src], m);
+    }
+
+    __device__ void t22(uint64_t *x0, uint64_t *x1, uint32_t e) const {
+        uint64_t D[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) D[r] = rot_diff(x0, x1, (uint32_t)r * S + l, e);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t k = (uint32_t)r * S + l;
+            x0[k] = madd(x0[k], x1[k], m);
+            x1[k] = D[r];
+        }
+    }
+    __device__ void t21(uint64_t *x0, uint64_t *x1, uint32_t e) const {
+        uint64_t D[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) D[r] = rot(x0, (uint32_t)r * S + l, e);
+#pragma unroll
+        for (int r = 0; r < R; ++r) x1[(uint32_t)r * S + l] = D[r];
+    }
+    __device__ void add2(uint64_t *x0, const uint64_t *x1) const {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t k = (uint32_t)r * S + l;
+            x0[k] = madd(x0[k], x1[k], m);
+        }
+    }
+    __device__ void i2(uint64_t *x0, uint64_t *x1, uint32_t einv) const {
+        uint64_t V[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) V[r] = rot(x1, (uint32_t)r * S + l, einv);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t k = (uint32_t)r * S + l;
+            const uint64_t a = x0[k];
+            x0[k] = madd(a, V[r], m);
+            x1[k] = msub(a, V[r], m);
+        }
+    }
+    // (x0, x1) <- (2 x0 - x1, y^e (x0 - x1)); z2 = false: x1 taken as 0
+    __device__ void i1f1(uint64_t *x0, uint64_t *x1, uint32_t e, bool z2) const {
+        uint64_t D[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t k = (uint32_t)r * S + l;
+            D[r] = z2 ? rot_diff(x0, x1, k, e) : rot(x0, k, e);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t k = (uint32_t)r * S + l;
+            const uint64_t a = x0[k];
+            x0[k] = z2 ? msub(madd(a, a, m), x1[k], m) : madd(a, a, m);
+            x1[k] = D[r];
+        }
+    }
+    __device__ void dbl_sub(uint64_t *x0, const uint64_t *x1) const {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t k = (uint32_t)r * S + l;
+            const uint64_t a = x0[k];
+            x0[k] = x1 ? msub(madd(a, a, m), x1[k], m) : madd(a, a, m);
+        }
+    }
+    __device__ void half(uint64_t *x0, const uint64_t *x1) const {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t k = (uint32_t)r * S + l;
+            x0[k] = mhalf(x1 ? madd(x0[k], x1[k], m) : x0[k], m);
+        }
+    }
+};
+
+template <int S, int R>
+__global__ void __launch_bounds__(512) nega_leaf_kernel(const Job *__restrict__ jobs,
+                                                         const LeafProg *__restrict__ progs,
+                                                         const LeafStep *__restrict__ steps,
+                                                         const LeafOp *__restrict__ ops, uint64_t *__restrict__ x,
+                                                         uint64_t m, uint32_t ord_mask, uint32_t job_offset) {
+    constexpr int K = S * R;
+    constexpr uint32_t G = 64 / S;
+    extern __shared__ uint64_t smq[];
+    const Job J = jobs[job_offset + blockIdx.x];
+    const LeafProg P = progs[J.prog];
+    const uint32_t tid = threadIdx.x, nthr = blockDim.x;
+    constexpr uint32_t KQ = K / 2;  // uint4 chunks per cell
+    for (uint32_t q = tid; q < J.nload * KQ; q += nthr) {
+        const uint32_t cell = q / KQ, off = q % KQ;
+        reinterpret_cast<uint4 *>(smq)[q] =
+            reinterpret_cast<const uint4 *>(x + (J.base + (uint64_t)cell * J.stride) * K)[off];
+    }
+    __syncthreads();
+    NegaSeg<S, R> B;
+    const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    B.l = lane & (S - 1);
+    B.m = m;
+    const uint32_t g = lane / S;
+    const uint32_t wave = tid >> 6, nwaves = nthr >> 6;
+    for (uint32_t st = 0; st < P.step_count; ++st) {
+        const LeafStep LS = steps[P.step_begin + st];
+        for (uint32_t jb = wave * G; jb < LS.op_count; jb += nwaves * G) {
+            const uint32_t j = jb + g;
+            if (j < LS.op_count) {
+                const LeafOp o = ops[LS.op_begin + j];
+                const uint32_t code = o.w0 & 15u;
+                const uint32_t i0 = (o.w0 >> 4) & 16383u, i1 = (o.w0 >> 18) & 16383u;
+                const uint32_t e =
+                    (uint32_t)((((uint64_t)J.s << (o.w1 >> 24)) + (uint64_t)(o.w1 & 0xFFFFFFu)) & ord_mask);
+                uint64_t *x0 = smq + (size_t)i0 * K, *x1 = smq + (size_t)i1 * K;
+                switch (code) {
+                    case OP_T22: B.t22(x0, x1, e); break;
+                    case OP_T21: B.t21(x0, x1, e); break;
+                    case OP_T12: B.add2(x0, x1); break;
+                    case OP_I2: B.i2(x0, x1, (0u - e) & ord_mask); break;
+                    case OP_I1F1Z2: B.i1f1(x0, x1, e, true); break;
+                    case OP_I1F1Z1: B.i1f1(x0, x1, e, false); break;
+                    case OP_I1F0Z2: B.dbl_sub(x0, x1); break;
+                    case OP_I1F0Z1: B.dbl_sub(x0, nullptr); break;
+                    case OP_I0Z2: B.half(x0, x1); break;
+                    case OP_I0Z1: B.half(x0, nullptr); break;
+                    default: break;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (uint32_t q = tid; q < J.nstore * KQ; q += nthr) {
+        const uint32_t cell = q / KQ, off = q % KQ;
+        reinterpret_cast<uint4 *>(x + (J.base + (uint64_t)cell * J.stride) * K)[off] =
+            reinterpret_cast<const uint4 *>(smq)[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// negacyclic products mod m with Montgomery reduction (R = 2^64)
+// ---------------------------------------------------------------------------
+
+// T = hi:lo < m 2^64  ->  T 2^-64 mod m
+__device__ __forceinline__ uint64_t redc(uint64_t lo, uint64_t hi, uint64_t m, uint64_t minv) {
+    const uint64_t u = lo * minv;
+    const uint64_t uhi = __umul64hi(u, m);
+    const uint64_t t = hi + uhi + (lo != 0 ? 1u : 0u);
+    return t >= m ? t - m : t;
+}
+
+constexpr int NP_COLS = 4;
+constexpr int NP_GROUP = 4;  // products per 128-bit partial sum: 4 m^2 < m 2^64 for m < 2^62
+
+template <int K>
+__global__ void __launch_bounds__(256) nega_pointwise_kernel(const uint64_t *__restrict__ a,
+                                                             const uint64_t *__restrict__ b, uint64_t *c, uint64_t m,
+                                                             uint64_t minv, uint64_t cfac) {
+    __shared__ uint64_t A[K], B[K];
+    const uint64_t i = blockIdx.x;
+    const uint32_t tid = threadIdx.x, nthr = blockDim.x;
+    for (uint32_t q = tid; q < (uint32_t)K; q += nthr) {
+        A[q] = a[i * K + q];
+        B[q] = b[i * K + q];
+    }
+    __syncthreads();
+    constexpr int NC = K < NP_COLS ? K : NP_COLS;
+    uint64_t res[NC];
+    bool have = false;
+    uint32_t k0 = tid * NC;
+    if (k0 < (uint32_t)K) {
+        have = true;
+        uint64_t pr[NC], nr[NC], plo[NC], phi[NC], nlo[NC], nhi[NC], bw[NC];
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) {
+            pr[cc] = nr[cc] = plo[cc] = phi[cc] = nlo[cc] = nhi[cc] = 0;
+            bw[cc] = B[(k0 + cc) & (K - 1)];
+        }
+        for (uint32_t ii = 0; ii < (uint32_t)K; ++ii) {
+            const uint64_t av = A[ii];
+#pragma unroll
+            for (int cc = 0; cc < NC; ++cc) {
+                const uint64_t lo = av * bw[cc], hi = __umul64hi(av, bw[cc]);
+                if (ii <= k0 + cc) {
+                    const uint64_t s = plo[cc] + lo;
+                    phi[cc] += hi + (s < lo ? 1u : 0u);
+                    plo[cc] = s;
+                } else {
+                    const uint64_t s = nlo[cc] + lo;
+                    nhi[cc] += hi + (s < lo ? 1u : 0u);
+                    nlo[cc] = s;
+                }
+            }
+            if ((ii & (NP_GROUP - 1)) == NP_GROUP - 1 || ii + 1 == (uint32_t)K) {
+#pragma unroll
+                for (int cc = 0; cc < NC; ++cc) {
+                    pr[cc] = madd(pr[cc], redc(plo[cc], phi[cc], m, minv), m);
+                    nr[cc] = madd(nr[cc], redc(nlo[cc], nhi[cc], m, minv), m);
+                    plo[cc] = phi[cc] = nlo[cc] = nhi[cc] = 0;
+                }
+            }
+#pragma unroll
+            for (int cc = NC - 1; cc > 0; --cc) bw[cc] = bw[cc - 1];
+            bw[0] = B[(k0 - ii - 1u) & (K - 1)];
+        }
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) {
+            // (pos - neg) 2^-64 -> times cfac = 2^128 2^-scale, reduced once more
+            const uint64_t d = msub(pr[cc], nr[cc], m);
+            res[cc] = redc(d * cfac, __umul64hi(d, cfac), m, minv);
+        }
+    }
+    __syncthreads();  // c may alias a or b
+    if (have) {
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) c[i * K + k0 + cc] = res[cc];
+    }
+}
+
+__global__ void nega_pack_kernel(const uint64_t *__restrict__ coef, uint64_t len, uint64_t *__restrict__ x,
+                                 uint64_t pieces, uint32_t K) {
+    const uint64_t total = pieces * K, half = K / 2;
+    for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < total;
+         q += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t p = q / K, j = q % K;
+        const uint64_t src = p * half + j;
+        x[q] = (j < half && src < len) ? coef[src] : 0u;
+    }
+}
+
+__global__ void nega_unpack_kernel(const uint64_t *__restrict__ x, uint64_t pieces, uint64_t *__restrict__ out,
+                                   uint64_t out_len, uint32_t K, uint64_t m) {
+    const uint64_t half = K / 2;
+    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < out_len;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t p = t / half, j = t % half;
+        uint64_t v = p < pieces ? x[p * K + j] : 0u;
+        if (p >= 1 && p - 1 < pieces) v = madd(v, x[(p - 1) * K + j + half], m);
+        out[t] = v;
+    }
+}
+
+template <int S, int R>
+hipError_t nega_leaf_launch(uint64_t m, uint32_t nwaves, uint32_t njobs, uint32_t lds_cells, const Job *jobs,
+                            uint32_t job_offset, const LeafProg *progs, const LeafStep *steps, const LeafOp *ops,
+                            uint64_t *x, uint32_t ord_mask, hipStream_t st) {
+    constexpr int K = S * R;
+    const size_t lds = (size_t)lds_cells * K * 8;
+    if (lds > kLdsBudget) return hipErrorInvalidValue;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&nega_leaf_kernel<S, R>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL((nega_leaf_kernel<S, R>), dim3(njobs), dim3(64 * nwaves), lds, st, jobs, progs, steps, ops, x,
+                       m, ord_mask, job_offset);
+    return hipGetLastError();
+}
+
+template <int K>
+hipError_t nega_pw_launch(uint64_t m, uint64_t n, const uint64_t *a, const uint64_t *b, uint64_t *c,
+                          uint32_t scale_log2, hipStream_t st) {
+    // host constants: minv = -m^-1 mod 2^64, cfac = 2^128 * 2^-scale mod m
+    uint64_t inv = 1;
+    for (int it = 0; it < 7; ++it) inv *= 2 - m * inv;  // Newton: m * inv = 1 mod 2^64
+    const uint64_t minv = 0 - inv;
+    unsigned __int128 r = ((unsigned __int128)1 << 64) % m;
+    r = (r * r) % m;  // 2^128 mod m
+    const uint64_t inv2 = (m + 1) / 2;
+    for (uint32_t t = 0; t < scale_log2; ++t) r = (r * inv2) % m;
+    const uint64_t cfac = (uint64_t)r;
+    uint32_t thr = (K + NP_COLS - 1) / NP_COLS;
+    thr = thr < 64 ? 64 : (thr > 256 ? 256 : thr);
+    thr = (thr + 63) / 64 * 64;
+    if ((uint32_t)K > thr * NP_COLS) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((nega_pointwise_kernel<K>), dim3((uint32_t)n), dim3(thr), 0, st, a, b, c, m, minv, cfac);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+#define TFT_NEGA_DISPATCH(K, FN, ...)              \
+    switch (K) {                                   \
+        case 2: return FN<2, 1>(__VA_ARGS__);      \
+        case 4: return FN<4, 1>(__VA_ARGS__);      \
+        case 8: return FN<8, 1>(__VA_ARGS__);      \
+        case 16: return FN<16, 1>(__VA_ARGS__);    \
+        case 32: return FN<32, 1>(__VA_ARGS__);    \
+        case 64: return FN<64, 1>(__VA_ARGS__);    \
+        case 128: return FN<64, 2>(__VA_ARGS__);   \
+        case 256: return FN<64, 4>(__VA_ARGS__);   \
+        case 512: return FN<64, 8>(__VA_ARGS__);   \
+        case 1024: return FN<64, 16>(__VA_ARGS__); \
+        case 2048: return FN<64, 32>(__VA_ARGS__); \
+        case 4096: return FN<64, 64>(__VA_ARGS__); \
+        default: return hipErrorInvalidValue;      \
+    }
+
+hipError_t launch_nega_leaf(uint32_t K, uint64_t m, uint32_t nwaves, uint32_t njobs, uint32_t lds_cells,
+                            const Job *jobs, uint32_t job_offset, const LeafProg *progs, const LeafStep *steps,
+                            const LeafOp *ops, uint64_t *x, uint32_t ord_mask, hipStream_t st) {
+    if (njobs == 0) return hipSuccess;
+    TFT_NEGA_DISPATCH(K, nega_leaf_launch, m, nwaves, njobs, lds_cells, jobs, job_offset, progs, steps, ops, x,
+                      ord_mask, st)
+}
+
+hipError_t launch_nega_pointwise(uint32_t K, uint64_t m, uint64_t n, const uint64_t *a, const uint64_t *b,
+                                 uint64_t *c, uint32_t scale_log2, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    switch (K) {
+        case 2: return nega_pw_launch<2>(m, n, a, b, c, scale_log2, st);
+        case 4: return nega_pw_launch<4>(m, n, a, b, c, scale_log2, st);
+        case 8: return nega_pw_launch<8>(m, n, a, b, c, scale_log2, st);
+        case 16: return nega_pw_launch<16>(m, n, a, b, c, scale_log2, st);
+        case 32: return nega_pw_launch<32>(m, n, a, b, c, scale_log2, st);
+        case 64: return nega_pw_launch<64>(m, n, a, b, c, scale_log2, st);
+        case 128: return nega_pw_launch<128>(m, n, a, b, c, scale_log2, st);
+        case 256: return nega_pw_launch<256>(m, n, a, b, c, scale_log2, st);
+        case 512: return nega_pw_launch<512>(m, n, a, b, c, scale_log2, st);
+        case 1024: return nega_pw_launch<1024>(m, n, a, b, c, scale_log2, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_nega_pack(uint32_t K, const uint64_t *coef, uint64_t len, uint64_t *x, uint64_t pieces,
+                            hipStream_t st) {
+    if (pieces == 0) return hipSuccess;
+    const uint64_t total = pieces * K;
+    uint32_t blocks = (uint32_t)((total + 255) / 256);
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(nega_pack_kernel, dim3(blocks), dim3(256), 0, st, coef, len, x, pieces, K);
+    return hipGetLastError();
+}
+
+hipError_t launch_nega_unpack(uint32_t K, uint64_t m, const uint64_t *x, uint64_t pieces, uint64_t *out,
+                              uint64_t out_len, hipStream_t st) {
+    if (out_len == 0) return hipSuccess;
+    uint32_t blocks = (uint32_t)((out_len + 255) / 256);
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(nega_unpack_kernel, dim3(blocks), dim3(256), 0, st, x, pieces, out, out_len, K, m);
+    return hipGetLastError();
+}
+
+}  // namespace tft

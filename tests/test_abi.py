@@ -1,0 +1,107 @@
+"""The C-ABI library loads, exports every declared symbol, and checks arguments.
+
+No compute call runs here: argument errors are reported before any device work,
+and plans are pure host objects.
+"""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_0810_3203_amd as T
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", fn)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_ ]*?\*?\s*\b([a-z_][a-z0-9_]*)\s*\(", src, re.M):
+            if m.group(1) not in ("if", "while", "for", "sizeof", "return"):
+                names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_symbols()
+    assert {"tft_forward", "itft_inverse", "pointwise_mul", "zx_mul_ss", "zmx_mul_nussbaumer"} <= names
+    lib = ctypes.CDLL(T.lib_path)
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings():
+    for st in range(7):
+        assert T.status_string(st)
+    assert T.status_string(1) == "invalid argument"
+
+
+def test_ring_check():
+    assert T.ring_check(T.fermat_ring(512)) == 0
+    assert T.ring_check(T.fermat_ring(65536)) == 0
+    assert T.ring_check(T.fermat_ring(96)) == 2       # W = 3 is not a power of two
+    assert T.ring_check(T.fermat_ring(100)) == 2      # N not a multiple of 32
+    assert T.ring_check(T.nega_ring(1024, (1 << 61) + 1)) == 0
+    assert T.ring_check(T.nega_ring(1024, 1 << 61)) == 2   # even modulus
+    assert T.ring_check(T.nega_ring(1000, 7)) == 2
+    assert T.elem_bytes(T.fermat_ring(512)) == 68
+    assert T.elem_bytes(T.nega_ring(1024, 7)) == 8192
+    assert T.array_bytes(T.fermat_ring(65536), 4) == 4 * 8196
+
+
+@pytest.mark.parametrize("args,code", [
+    ((0, 0, 1, 1), 1),        # l = 0
+    ((5, 0, 0, 1), 1),        # z = 0
+    ((5, 0, 33, 1), 1),       # z > L
+    ((5, 0, 1, 0), 1),        # n = 0
+    ((5, 0, 1, 33), 1),       # n > L
+    ((12, 0, 1, 1), 2),       # L = 4096 does not divide 2N = 1024
+])
+def test_tft_forward_rejects_bad_arguments(args, code):
+    l, s, z, n = args
+    rc = T.lib().tft_forward(ctypes.byref(T.fermat_ring(512)), l, s, z, n, ctypes.c_void_p(1), None)
+    assert rc == code
+
+
+@pytest.mark.parametrize("args,code", [
+    ((5, 0, 10, 11, 0), 1),   # z < n
+    ((5, 0, 10, 5, 2), 1),    # f not in {0, 1}
+    ((5, 0, 32, 32, 1), 1),   # n + f > L
+    ((5, 0, 10, 0, 0), 1),    # n + f = 0
+])
+def test_itft_rejects_bad_arguments(args, code):
+    l, s, z, n, f = args
+    rc = T.lib().itft_inverse(ctypes.byref(T.fermat_ring(512)), l, s, z, n, f, ctypes.c_void_p(1), None)
+    assert rc == code
+
+
+def test_product_argument_errors():
+    L = T.lib()
+    # output limbs too small: 64-bit inputs need 128 + log2(min len) bits
+    rc = L.zx_mul_ss(ctypes.c_void_p(1), 10, 2, ctypes.c_void_p(1), 10, 2, ctypes.c_void_p(1), 4, None,
+                     ctypes.c_void_p(1), 1 << 30, None)
+    assert rc == 3
+    # workspace too small
+    rc = L.zx_mul_ss(ctypes.c_void_p(1), 10, 2, ctypes.c_void_p(1), 10, 2, ctypes.c_void_p(1), 6, None,
+                     ctypes.c_void_p(1), 16, None)
+    assert rc == 4
+    # SN: transform length above 2K
+    rc = L.zmx_mul_nussbaumer(ctypes.c_void_p(1), 10000, ctypes.c_void_p(1), 10000, 7, 4, ctypes.c_void_p(1),
+                              ctypes.c_void_p(1), 1 << 30, None)
+    assert rc == 1
+    assert T.zx_mul_ss_workspace(500, 2, 500, 2) == 2 * 1024 * 17 * 4
+
+
+def test_plans_are_host_objects():
+    p = T.Plan(T.fermat_ring(512), 0, 10, 0, 500, 999)
+    d = p.export()
+    assert d["ord"] == 1024 and d["passes"] and p.base_cases > 0
+    p.close()
+    with pytest.raises(T.TFTError):
+        T.Plan(T.fermat_ring(512), 1, 10, 0, 10, 11)

@@ -104,6 +104,24 @@ def test_principal_root_identity(ring):
             assert ring.eq(acc, ring.zero())
 
 
+def test_fermat_mul_theta_is_product_with_theta_power():
+    rng = random.Random(19)
+    for N in (2, 4, 8, 64, 96, 512):
+        ring = O.FermatRing(N)
+        for _ in range(60):
+            a = rng.choice([0, 1, ring.p - 1, rng.randrange(ring.p)])
+            e = rng.randrange(-2 * ring.ord, 3 * ring.ord)
+            assert ring.mul_theta(a, e) == (a * pow(2, e % ring.ord, ring.p)) % ring.p
+
+
+def test_nega_mul_theta_is_product_with_theta_power():
+    ring = O.NegaRing(8, 1000003)
+    rng = random.Random(17)
+    for e in range(-3, 2 * ring.K + 3):
+        a = tuple(rng.randrange(ring.m) for _ in range(ring.K))
+        assert ring.mul_theta(a, e) == ring.mul(a, ring.theta_pow(e))
+
+
 def test_two_is_invertible():
     for ring in RINGS:
         for k in range(0, 5):

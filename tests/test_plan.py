@@ -1,0 +1,205 @@
+"""The host planner's expansion of Alg. 1 and Alg. 2, checked on the CPU.
+
+The schedule exported by the library is executed with exact arithmetic
+(tests/plan_sim.py) and compared with the oracle's eq. (1) / ITFT definition,
+for both rings, many (z, n, f, zeta) and every split policy.  Base-case counts
+are checked against Theorems 1 and 2, and the phase structure against the
+shapes of Fig. 7 and the partition example of Sect. 6.
+"""
+
+import os
+import random
+
+import pytest
+
+import paper_0810_3203_amd as T
+from oracle import tft_oracle as O
+from tests.plan_sim import simulate
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rand(ring, rng):
+    if ring.kind == "fermat":
+        # canonical residues including the extreme ones
+        k = rng.randrange(8)
+        if k == 0:
+            return ring.p - 1  # 2^N
+        if k == 1:
+            return 0
+        return rng.randrange(ring.p)
+    return tuple(rng.randrange(ring.m) for _ in range(ring.K))
+
+
+def _lib_ring(ring):
+    return T.fermat_ring(ring.N) if ring.kind == "fermat" else T.nega_ring(ring.K, ring.m)
+
+
+def _check_tft(ring, l, s, z, n, top_l1=0, leaf_log2=0, seed=0):
+    rng = random.Random(seed)
+    L = 1 << l
+    a = [_rand(ring, rng) for _ in range(L)]  # cells >= z hold garbage
+    plan = T.Plan(_lib_ring(ring), 0, l, s, z, n, 0, top_l1, leaf_log2)
+    x = simulate(plan.export(), ring, list(a), seed + 1)
+    assert x[:n] == O.tft(ring, L, s, z, n, a[:z]), (l, s, z, n, top_l1, leaf_log2)
+    return plan
+
+
+def _check_itft(ring, l, s, z, n, f, top_l1=0, leaf_log2=0, seed=0):
+    rng = random.Random(seed)
+    L = 1 << l
+    a = [_rand(ring, rng) for _ in range(z)]
+    inputs, expect = O.itft_case(ring, L, s, z, n, f, a)
+    x = list(inputs) + [_rand(ring, rng) for _ in range(L - z)]
+    plan = T.Plan(_lib_ring(ring), 1, l, s, z, n, f, top_l1, leaf_log2)
+    x = simulate(plan.export(), ring, x, seed + 1)
+    assert x[:n + f] == expect, (l, s, z, n, f, top_l1, leaf_log2)
+    return plan
+
+
+FERMAT = O.FermatRing(64)     # ord 128
+NEGA = O.NegaRing(16, 1000003)  # ord 32
+
+
+@pytest.mark.parametrize("leaf_log2", [1, 2, 3, 0])
+def test_tft_schedule_matches_eq1_fermat(leaf_log2):
+    rng = random.Random(leaf_log2)
+    for l in (1, 2, 3, 4, 5, 6):
+        L = 1 << l
+        cases = {(1, 1), (L, L), (1, L), (L, 1)}
+        while len(cases) < min(8, L * L):
+            cases.add((rng.randint(1, L), rng.randint(1, L)))
+        for z, n in sorted(cases):
+            s = rng.randrange(128)
+            _check_tft(FERMAT, l, s, z, n, 0, leaf_log2, seed=z * 131 + n)
+
+
+@pytest.mark.parametrize("leaf_log2", [1, 2, 3, 0])
+def test_itft_schedule_matches_definition_fermat(leaf_log2):
+    rng = random.Random(100 + leaf_log2)
+    for l in (1, 2, 3, 4, 5, 6):
+        L = 1 << l
+        cases = set()
+        for z in {1, L, rng.randint(1, L), rng.randint(1, L)}:
+            for n in {0, z, rng.randint(0, z), max(0, z - 1)}:
+                for f in (0, 1):
+                    if 1 <= n + f <= L:
+                        cases.add((z, n, f))
+        for z, n, f in sorted(cases):
+            s = rng.randrange(128)
+            _check_itft(FERMAT, l, s, z, n, f, 0, leaf_log2, seed=z * 7 + n)
+
+
+@pytest.mark.parametrize("top_l1", [1, 2, 3, 4])
+def test_every_top_split_gives_the_same_outputs(top_l1):
+    rng = random.Random(top_l1)
+    l = 5
+    for _ in range(6):
+        z, n = rng.randint(1, 32), rng.randint(1, 32)
+        _check_tft(FERMAT, l, rng.randrange(128), z, n, top_l1, 2, seed=z + 100 * n)
+        zi = rng.randint(1, 32)
+        ni = rng.randint(0, zi)
+        f = rng.randint(0 if ni else 1, 1 if ni < 32 else 0)
+        _check_itft(FERMAT, l, rng.randrange(128), zi, ni, f, top_l1, 2, seed=zi + 100 * ni)
+
+
+def test_nega_ring_schedules():
+    rng = random.Random(5)
+    for l in (1, 3, 5):
+        L = 1 << l
+        for _ in range(5):
+            z, n = rng.randint(1, L), rng.randint(1, L)
+            _check_tft(NEGA, l, rng.randrange(32), z, n, 0, rng.choice([1, 2, 0]), seed=z + n)
+            zi = rng.randint(1, L)
+            ni = rng.randint(0, zi)
+            f = 1 if ni == 0 else rng.randint(0, 1 if ni < L else 0)
+            _check_itft(NEGA, l, rng.randrange(32), zi, ni, f, 0, rng.choice([1, 2, 0]), seed=zi + ni)
+
+
+def test_polynomial_product_through_the_schedule():
+    """Sect. 2: TFT(g), TFT(h), n products, ITFT(L, 1, n, n, 0) gives L (g h)."""
+    ring = FERMAT
+    rng = random.Random(8)
+    l, L = 6, 64
+    g = [rng.randrange(1 << 20) for _ in range(21)]
+    h = [rng.randrange(1 << 20) for _ in range(30)]
+    n = len(g) + len(h) - 1
+    pg = T.Plan(_lib_ring(ring), 0, l, 0, len(g), n, 0, 0, 2).export()
+    ph = T.Plan(_lib_ring(ring), 0, l, 0, len(h), n, 0, 0, 2).export()
+    xg = simulate(pg, ring, g + [0] * (L - len(g)))
+    xh = simulate(ph, ring, h + [0] * (L - len(h)))
+    u = [ring.mul(a, b) for a, b in zip(xg[:n], xh[:n])] + [0] * (L - n)
+    pi = T.Plan(_lib_ring(ring), 1, l, 0, n, n, 0, 0, 2).export()
+    u = simulate(pi, ring, u)
+    assert [ring.mul(v, ring.inv_pow2(l)) for v in u[:n]] == O.zx_mul(g, h)
+
+
+# ---------------------------------------------------------------------------
+# base-case counts (Theorems 1 and 2)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("leaf_log2", [1, 0])
+def test_base_case_counts_within_theorem_bounds(leaf_log2):
+    rng = random.Random(leaf_log2 + 9)
+    ring = T.fermat_ring(2048)  # ord 4096
+    for l in range(1, 13):
+        L = 1 << l
+        for _ in range(6):
+            z, n = rng.randint(1, L), rng.randint(1, L)
+            p = T.Plan(ring, 0, l, 0, z, n, 0, 0, leaf_log2)
+            # Theorem 1: at most min((n-1) l/2 + L - 1, L l/2)
+            assert 2 * p.base_cases <= min((n - 1) * l + 2 * (L - 1), L * l), (l, z, n, p.base_cases)
+            zi = rng.randint(1, L)
+            ni = rng.randint(0, zi)
+            f = 1 if ni == 0 else (0 if ni == L else rng.randint(0, 1))
+            q = T.Plan(ring, 1, l, 0, zi, ni, f, 0, leaf_log2)
+            # Theorem 2: at most min((n+f-1) l/2 + L - 1, L l/2)
+            assert 2 * q.base_cases <= min((ni + f - 1) * l + 2 * (L - 1), L * l), (l, zi, ni, f, q.base_cases)
+
+
+# Exact counts with the paper's split at every level (leaf length 2), for the
+# benchmark shapes: (ring, l, z, n) -> (TFT count, ITFT count with z = n, f = 0).
+EXACT = [
+    (T.fermat_ring(512), 10, 500, 999, 5064, 5076),
+    (T.fermat_ring(4096), 13, 3000, 5999, 40408, 41504),
+    (T.nega_ring(1024, 3), 11, 977, 1953, 10976, 11023),
+]
+
+
+@pytest.mark.parametrize("ring,l,z,n,ct,ci", EXACT)
+def test_exact_counts_paper_split(ring, l, z, n, ct, ci):
+    assert T.Plan(ring, 0, l, 0, z, n, 0, 0, 1).base_cases == ct
+    assert T.Plan(ring, 1, l, 0, n, n, 0, 0, 1).base_cases == ci
+
+
+def test_exact_counts_large_case():
+    ring = T.fermat_ring(65536)
+    assert T.Plan(ring, 0, 17, 0, 50000, 99999, 0, 0, 1).base_cases == 893504
+    assert T.Plan(ring, 1, 17, 0, 99999, 99999, 0, 0, 1).base_cases == 909040
+
+
+# ---------------------------------------------------------------------------
+# phase structure: Fig. 7 and Sect. 6
+# ---------------------------------------------------------------------------
+
+def test_fig7_cases_phase_structure():
+    rows = [ln for ln in open(os.path.join(GOLDEN, "itft_fig7_cases.txt")) if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 4
+    for ln in rows:
+        head, tail = ln.split("|")
+        _, z, n = head.split()
+        expect = [int(v) for v in tail.split()]
+        d = T.Plan(T.fermat_ring(1024), 1, 6, 0, int(z), int(n), 0, 0, 3).export()
+        assert [p[1] for p in d["passes"]] == expect, ln
+
+
+def test_sec6_partition():
+    ln = [ln for ln in open(os.path.join(GOLDEN, "sec6_partition.txt")) if ln.strip() and not ln.startswith("#")][0]
+    head, tail = ln.split("|")
+    l, l1, n = (int(v) for v in head.split())
+    full, part = (int(v) for v in tail.split())
+    d = T.Plan(T.fermat_ring(32 * 256), 0, l, 0, n, n, 0, 0, l1).export()
+    assert len(d["passes"]) == 2
+    jb, jc, _ = d["passes"][1]
+    stores = [j[5] for j in d["jobs"][jb:jb + jc]]
+    assert stores.count(1 << (l - l1)) == full and stores.count(part) == 1 and len(stores) == full + 1
