@@ -81,6 +81,10 @@ typedef struct {
 /* Human-readable name of a status code (static string). */
 const char *tft_status_string(int status);
 
+/* Text of the last HIP failure seen by this thread ("" if none): the failing
+ * call and HIP's error string.  Set whenever an entry point returns TFT_E_DEVICE. */
+const char *tft_last_error(void);
+
 /* TFT_OK if the ring is supported by this build (see tft_ring). */
 int tft_ring_check(const tft_ring *ring);
 

@@ -64,6 +64,8 @@ def lib():
         RP = ctypes.POINTER(Ring)
         L.tft_status_string.argtypes = [I]
         L.tft_status_string.restype = ctypes.c_char_p
+        L.tft_last_error.argtypes = []
+        L.tft_last_error.restype = ctypes.c_char_p
         L.tft_ring_check.argtypes = [RP]
         L.tft_ring_check.restype = I
         L.tft_elem_bytes.argtypes = [RP]
@@ -104,6 +106,8 @@ def status_string(status: int) -> str:
 
 def _check(rc, where):
     if rc != 0:
+        if rc == 5:
+            where = "%s [%s]" % (where, lib().tft_last_error().decode())
         raise TFTError(rc, where)
 
 

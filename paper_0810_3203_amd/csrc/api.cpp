@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -73,7 +75,17 @@ uint32_t max_leaf_log2(const tft_ring *r) {
     return std::min<uint32_t>(lg, 11);
 }
 
-int hip_status(hipError_t e) { return e == hipSuccess ? TFT_OK : TFT_E_DEVICE; }
+thread_local char g_last_error[256] = "";
+
+// Records the HIP error of a failed call (readable through tft_last_error) and
+// prints it when TFT_DEBUG is set in the environment.
+int dev_fail(hipError_t e, const char *where) {
+    snprintf(g_last_error, sizeof g_last_error, "%s: %s (%d)", where, hipGetErrorString(e), (int)e);
+    if (getenv("TFT_DEBUG")) fprintf(stderr, "[tft] %s\n", g_last_error);
+    return TFT_E_DEVICE;
+}
+
+int hip_status(hipError_t e, const char *where = "launch") { return e == hipSuccess ? TFT_OK : dev_fail(e, where); }
 
 int check_transform_args(const tft_ring *ring, uint32_t dir, uint32_t l, uint64_t z, uint64_t n, uint32_t f) {
     int st = check_ring(ring);
@@ -91,14 +103,16 @@ int check_transform_args(const tft_ring *ring, uint32_t dir, uint32_t l, uint64_
 
 int plan_upload(tft_plan *p) {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return TFT_E_DEVICE;
+    hipError_t ge = hipGetDevice(&dev);
+    if (ge != hipSuccess) return dev_fail(ge, "hipGetDevice");
     if (p->dev && p->dev_id == dev) return TFT_OK;
     const Schedule &S = p->sched;
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
     const size_t bj = al(S.jobs.size() * sizeof(Job)), bp = al(S.progs.size() * sizeof(LeafProg));
     const size_t bs = al(S.steps.size() * sizeof(LeafStep)), bo = al(std::max<size_t>(1, S.ops.size()) * sizeof(LeafOp));
     void *buf = nullptr;
-    if (hipMalloc(&buf, bj + bp + bs + bo) != hipSuccess) return TFT_E_DEVICE;
+    hipError_t me = hipMalloc(&buf, bj + bp + bs + bo);
+    if (me != hipSuccess) return dev_fail(me, "hipMalloc(plan)");
     char *c = static_cast<char *>(buf);
     hipError_t e = hipSuccess;
     if (!S.jobs.empty()) e = hipMemcpy(c, S.jobs.data(), S.jobs.size() * sizeof(Job), hipMemcpyHostToDevice);
@@ -110,7 +124,7 @@ int plan_upload(tft_plan *p) {
         e = hipMemcpy(c + bj + bp + bs, S.ops.data(), S.ops.size() * sizeof(LeafOp), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(buf);
-        return TFT_E_DEVICE;
+        return dev_fail(e, "hipMemcpy(plan)");
     }
     if (p->dev) (void)hipFree(p->dev);
     p->dev = buf;
@@ -161,7 +175,7 @@ int plan_run(tft_plan *p, void *x, hipStream_t st) {
             e = launch_nega_leaf(p->ring.K, p->ring.m, p->nwaves[i], pd.job_count, pd.max_len, p->d_jobs,
                                  pd.job_begin, p->d_progs, p->d_steps, p->d_ops, static_cast<uint64_t *>(x), ord_mask,
                                  st);
-        if (e != hipSuccess) return TFT_E_DEVICE;
+        if (e != hipSuccess) return dev_fail(e, "leaf pass");
     }
     return TFT_OK;
 }
@@ -185,6 +199,8 @@ tft_plan *cached_plan(const tft_ring *ring, uint32_t dir, uint32_t l, uint64_t s
 }  // namespace
 
 extern "C" {
+
+const char *tft_last_error(void) { return g_last_error; }
 
 const char *tft_status_string(int status) {
     switch (status) {
@@ -377,13 +393,13 @@ int zx_mul_ss(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uint32_
     const tft_split *split = params ? &params->split : nullptr;
     hipError_t e = launch_fermat_pack(sh.W, g, len_g, g_limbs, A, sh.L, hs);
     if (e == hipSuccess) e = launch_fermat_pack(sh.W, h, len_h, h_limbs, B, sh.L, hs);
-    if (e != hipSuccess) return TFT_E_DEVICE;
+    if (e != hipSuccess) return dev_fail(e, "pack");
     st = plan_run(cached_plan(&ring, 0, sh.l, 0, len_g, sh.n, 0, split), A, hs);
     if (st) return st;
     st = plan_run(cached_plan(&ring, 0, sh.l, 0, len_h, sh.n, 0, split), B, hs);
     if (st) return st;
     e = launch_fermat_pointwise(sh.W, sh.n, A, B, A, sh.L, (uint32_t)((2 * sh.N - sh.l) % (2 * sh.N)), hs);
-    if (e != hipSuccess) return TFT_E_DEVICE;
+    if (e != hipSuccess) return dev_fail(e, "pointwise");
     st = plan_run(cached_plan(&ring, 1, sh.l, 0, sh.n, sh.n, 0, split), A, hs);
     if (st) return st;
     return hip_status(launch_fermat_unpack(sh.W, A, sh.L, sh.n, out, out_limbs, hs));
@@ -436,13 +452,13 @@ int zmx_mul_nussbaumer(const uint64_t *g, uint64_t len_g, const uint64_t *h, uin
     uint64_t *B = A + sh.L * sh.K;
     hipError_t e = launch_nega_pack(sh.K, g, len_g, A, sh.zg, hs);
     if (e == hipSuccess) e = launch_nega_pack(sh.K, h, len_h, B, sh.zh, hs);
-    if (e != hipSuccess) return TFT_E_DEVICE;
+    if (e != hipSuccess) return dev_fail(e, "pack");
     st = plan_run(cached_plan(&ring, 0, sh.l, 0, sh.zg, sh.n, 0, nullptr), A, hs);
     if (st) return st;
     st = plan_run(cached_plan(&ring, 0, sh.l, 0, sh.zh, sh.n, 0, nullptr), B, hs);
     if (st) return st;
     e = launch_nega_pointwise(sh.K, m, sh.n, A, B, A, sh.l, hs);
-    if (e != hipSuccess) return TFT_E_DEVICE;
+    if (e != hipSuccess) return dev_fail(e, "pointwise");
     st = plan_run(cached_plan(&ring, 1, sh.l, 0, sh.n, sh.n, 0, nullptr), A, hs);
     if (st) return st;
     return hip_status(launch_nega_unpack(sh.K, m, A, sh.n, out, len_g + len_h - 1, hs));

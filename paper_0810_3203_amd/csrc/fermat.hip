@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(256) fermat_pointwise_kernel(const uint32_t *_
     uint32_t *A = sm, *Bv = A + W;
     uint32_t *P0 = Bv + W, *P1 = P0 + W, *P2 = P1 + W, *N0 = P2 + W, *N1 = N0 + W, *N2 = N1 + W;
     uint32_t *Y = N2 + W;
-    __shared__ uint32_t topY;
+    uint32_t &topY = Y[W];
     const uint64_t i = blockIdx.x;
     const uint32_t tid = threadIdx.x, nthr = blockDim.x;
 
@@ -313,10 +313,10 @@ template <int S, int R>
 hipError_t pointwise_launch(uint64_t n, const uint32_t *a, const uint32_t *b, uint32_t *c, uint64_t cap,
                             uint32_t scale_e, hipStream_t st) {
     constexpr int W = S * R;
-    const size_t lds = (size_t)9 * W * 4;
+    const size_t lds = (size_t)(9 * W + 1) * 4;
     if (lds > kLdsBudget) return hipErrorInvalidValue;
     static bool attr = false;
-    if (!attr) {
+    if (!attr && lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fermat_pointwise_kernel<S, R>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
         if (e != hipSuccess) return e;
