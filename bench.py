@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Benchmark of the cache-friendly TFT hot path on one MI355X.
+
+Workload (one step = the whole hot path over one batch of synthetic input):
+the large-coefficient Schoenhage-Strassen product in Z[x] -- two polynomials
+of 50,000 coefficients of 32,000 bits, ring Z/(2^65536+1), transform length
+L = 2^17 split 2^8 x 2^9, truncation n = 99,999: pack, TFT(g), TFT(h),
+99,999 pointwise products, ITFT, unpack (zx_mul_ss).
+
+Metric: TFT+ITFT throughput in GB/s of algorithmic bytes -- the cells each
+transform's top-level column and row passes read and write (Alg. 1 and
+Alg. 2 loop bounds, 8192 bytes per cell) -- over the time of the three
+transforms, measured with HIP events on the stream the kernels run on.
+Inputs are resident in HBM before the timed region.  One JSON line is printed.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "TFT+ITFT GB/s & % HBM peak; batched Z[x] muls/s vs one-at-a-time (bit-exact)"
+HBM_PEAK_GBS = 8000.0
+
+
+def _split(l):
+    return l // 2, l - l // 2
+
+
+def alg_cells_tft(l, z, n):
+    """Cells read + written by Alg. 1's top-level column and row passes."""
+    l1, l2 = _split(l)
+    L2 = 1 << l2
+    n1p = -(-n // L2)
+    z1, z2 = divmod(z, L2)
+    z2p = L2 if z1 else z2
+    return z + z2p * n1p + n1p * z2p + n
+
+
+def alg_cells_itft(l, z, n, f):
+    """Cells read + written by Alg. 2's top-level rows, right columns, last row and left columns."""
+    l1, l2 = _split(l)
+    L2 = 1 << l2
+    n1, n2 = divmod(n, L2)
+    z1, z2 = divmod(z, L2)
+    fp = 1 if n2 + f > 0 else 0
+    z2p = L2 if z1 else z2
+    m, mp = min(n2, z2), max(n2, z2)
+    cells = n1 * L2 * 2
+    for u in range(n2, z2p):
+        cells += (z1 + 1 if u < mp else z1) + n1 + fp
+    if fp:
+        cells += z2p + n2 + f
+    for u in range(n2):
+        cells += (z1 + 1 if u < m else z1) + n1 + 1
+    return cells
+
+
+def cpu_baseline(g_limbs_arr, N, l, z, n, alg_bytes, budget_s=15.0):
+    """The oracle (eq. (1) evaluated directly, plain C) on a bounded sample, extrapolated."""
+    import numpy as np
+    from oracle import coracle
+    threads = min(16, os.cpu_count() or 1)
+    L = 1 << l
+    W = N // 32
+    a = np.zeros((z, W), dtype=np.uint32)
+    a[:, : g_limbs_arr.shape[1]] = g_limbs_arr[:z]
+    tops = np.zeros(z, dtype=np.uint32)
+    # one probe output to size the sample, then a batch of outputs on all threads
+    t0 = time.perf_counter()
+    coracle.fermat_dft_sampled(N, L, 0, a, tops, [1], nthreads=1)
+    t_one = time.perf_counter() - t0
+    k = max(threads, min(4 * threads, int(budget_s * threads / max(t_one, 1e-6))))
+    js = [(7919 * i) % n for i in range(k)]
+    t0 = time.perf_counter()
+    coracle.fermat_dft_sampled(N, L, 0, a, tops, js, nthreads=threads)
+    t_k = time.perf_counter() - t0
+    per_output = t_k / k  # wall seconds per TFT output (z terms) with `threads` threads
+    # the direct transforms: 2 TFTs of n outputs with z terms, one inverse of n outputs with n terms
+    total_s = per_output * (2 * n + n * (n / z))
+    return {"value": alg_bytes / total_s / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": "eq. (1) evaluated directly for %d output indices of TFT(g) (%d terms each) on %d threads, "
+                      "%.1f s; extrapolated by term count to TFT(g)+TFT(h)+ITFT (%.0f s)" % (k, z, threads, t_k,
+                                                                                          total_s)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_0810_3203_amd as T
+    from synth import workloads as wl
+
+    torch.cuda.set_device(0)
+    spec = wl.ZX_CASES[3]
+    g, h = wl.zx_operands(3)
+    len_g, len_h = g.shape[0], h.shape[0]
+    n = len_g + len_h - 1
+    N, l = spec["N"], spec["l"]
+    out_limbs = (32 * (g.shape[1] + h.shape[1]) + (min(len_g, len_h) - 1).bit_length() + 31) // 32
+    dg = torch.from_numpy(g.view(np.int32)).cuda()
+    dh = torch.from_numpy(h.view(np.int32)).cuda()
+    out = torch.empty((n, out_limbs), dtype=torch.int32, device="cuda")
+    ws = torch.empty(T.zx_mul_ss_workspace(len_g, g.shape[1], len_h, h.shape[1]), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+
+    cell_bytes = N // 8
+    cells = alg_cells_tft(l, len_g, n) + alg_cells_tft(l, len_h, n) + alg_cells_itft(l, n, n, 0)
+    alg_bytes = cells * cell_bytes
+
+    for _ in range(args.warmup):
+        T.zx_mul_ss_timed(dg, dh, out, ws=ws)
+    torch.cuda.synchronize()
+    phases = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        phases.append(T.zx_mul_ss_timed(dg, dh, out, ws=ws))
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+
+    def avg(key):
+        return sum(p[key] for p in phases) / len(phases)
+
+    transform_ms = avg("tft_g_ms") + avg("tft_h_ms") + avg("itft_ms")
+    leaf_ms = avg("leaf_kernel_ms")
+    launches = phases[0]["leaf_launches"]
+    value = alg_bytes / (transform_ms * 1e-3) / 1e9
+    achieved = alg_bytes / (leaf_ms * 1e-3) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall_ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": "Z[x] product by Schoenhage-Strassen: 50000 x 50000 coefficients of 32000 bits, "
+                        "R = Z/(2^65536+1), L = 2^17 (2^8 x 2^9), n = 99999",
+            "alg_cells": cells,
+            "alg_bytes": alg_bytes,
+            "phases_ms": {k: round(avg(k), 3) for k in ("pack_ms", "tft_g_ms", "tft_h_ms", "pointwise_ms",
+                                                         "itft_ms", "unpack_ms", "total_ms")},
+            "transform_ms": round(transform_ms, 3),
+            "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "kernel": "fermat_leaf_kernel<64,32> (%d launches per step)" % launches,
+            "avg_launch_ms": round(leaf_ms / max(1, launches), 4),
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(g, N, l, len_g, n, alg_bytes)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -146,6 +146,22 @@ int zx_mul_ss(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uint32_
               uint32_t h_limbs, uint32_t *out, uint32_t out_limbs, const tft_ss_params *params, void *ws,
               uint64_t ws_bytes, void *stream);
 
+/* Phase times of one zx_mul_ss call, from HIP events recorded on its stream. */
+typedef struct {
+    float pack_ms, tft_g_ms, tft_h_ms, pointwise_ms, itft_ms, unpack_ms, total_ms;
+    float leaf_kernel_ms;    /* summed durations of the transform (leaf) kernel launches */
+    uint32_t leaf_launches;  /* leaf kernel launches of the three transforms */
+    uint32_t n;              /* product length len_g + len_h - 1 */
+    uint32_t l;              /* transform length 2^l used */
+    uint32_t N;              /* ring Z/(2^N+1) used */
+} tft_ss_timing;
+
+/* zx_mul_ss, also filling *timing; waits for the work to finish before returning.
+ * For measurement: the events add a few microseconds per launch. */
+int zx_mul_ss_timed(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uint32_t *h, uint64_t len_h,
+                    uint32_t h_limbs, uint32_t *out, uint32_t out_limbs, const tft_ss_params *params, void *ws,
+                    uint64_t ws_bytes, void *stream, tft_ss_timing *timing);
+
 /* Workspace bytes zmx_mul_nussbaumer needs. */
 int zmx_mul_nussbaumer_workspace(uint64_t len_g, uint64_t len_h, uint32_t log2K, uint64_t *bytes);
 

@@ -27,11 +27,12 @@ from ._binding import (  # noqa: F401
     zmx_mul_nussbaumer,
     zmx_mul_nussbaumer_workspace,
     zx_mul_ss,
+    zx_mul_ss_timed,
     zx_mul_ss_workspace,
 )
 
 __all__ = [
     "FERMAT", "NEGA", "Plan", "SSParams", "Split", "TFTError", "array_bytes", "elem_bytes", "fermat_ring",
     "itft_inverse", "lib", "lib_path", "nega_ring", "pointwise_mul", "ring_check", "status_string", "tft_forward",
-    "zmx_mul_nussbaumer", "zmx_mul_nussbaumer_workspace", "zx_mul_ss", "zx_mul_ss_workspace",
+    "zmx_mul_nussbaumer", "zmx_mul_nussbaumer_workspace", "zx_mul_ss", "zx_mul_ss_timed", "zx_mul_ss_workspace",
 ]

@@ -37,6 +37,16 @@ class Split(ctypes.Structure):
     _fields_ = [("top_l1", ctypes.c_uint32), ("leaf_log2", ctypes.c_uint32)]
 
 
+class SSTiming(ctypes.Structure):
+    _fields_ = [("pack_ms", ctypes.c_float), ("tft_g_ms", ctypes.c_float), ("tft_h_ms", ctypes.c_float),
+                ("pointwise_ms", ctypes.c_float), ("itft_ms", ctypes.c_float), ("unpack_ms", ctypes.c_float),
+                ("total_ms", ctypes.c_float), ("leaf_kernel_ms", ctypes.c_float), ("leaf_launches", ctypes.c_uint32),
+                ("n", ctypes.c_uint32), ("l", ctypes.c_uint32), ("N", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class SSParams(ctypes.Structure):
     _fields_ = [("N", ctypes.c_uint32), ("l", ctypes.c_uint32), ("split", Split)]
 
@@ -82,6 +92,9 @@ def lib():
         L.zx_mul_ss_workspace.restype = I
         L.zx_mul_ss.argtypes = [P, U64, U32, P, U64, U32, P, U32, ctypes.POINTER(SSParams), P, U64, P]
         L.zx_mul_ss.restype = I
+        L.zx_mul_ss_timed.argtypes = [P, U64, U32, P, U64, U32, P, U32, ctypes.POINTER(SSParams), P, U64, P,
+                                      ctypes.POINTER(SSTiming)]
+        L.zx_mul_ss_timed.restype = I
         L.zmx_mul_nussbaumer_workspace.argtypes = [U64, U64, U32, ctypes.POINTER(U64)]
         L.zmx_mul_nussbaumer_workspace.restype = I
         L.zmx_mul_nussbaumer.argtypes = [P, U64, P, U64, U64, U32, P, P, U64, P]
@@ -173,6 +186,21 @@ def zx_mul_ss(g, h, out, params=None, ws=None, stream=None):
                            ctypes.byref(params) if params else None, _ptr(ws), ws.numel() * ws.element_size(),
                            _stream(stream)), "zx_mul_ss")
     return out
+
+
+def zx_mul_ss_timed(g, h, out, params=None, ws=None, stream=None):
+    """zx_mul_ss that waits for completion and returns the phase times (SSTiming.as_dict())."""
+    len_g, g_limbs = g.shape
+    len_h, h_limbs = h.shape
+    need = zx_mul_ss_workspace(len_g, g_limbs, len_h, h_limbs, params)
+    if ws is None:
+        import torch
+        ws = torch.empty(need, dtype=torch.uint8, device=g.device)
+    tm = SSTiming()
+    _check(lib().zx_mul_ss_timed(_ptr(g), len_g, g_limbs, _ptr(h), len_h, h_limbs, _ptr(out), out.shape[1],
+                                 ctypes.byref(params) if params else None, _ptr(ws), ws.numel() * ws.element_size(),
+                                 _stream(stream), ctypes.byref(tm)), "zx_mul_ss_timed")
+    return tm.as_dict()
 
 
 def zmx_mul_nussbaumer_workspace(len_g, len_h, log2K) -> int:

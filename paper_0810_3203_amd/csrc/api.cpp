@@ -159,7 +159,36 @@ tft_plan *plan_build(const tft_ring *ring, uint32_t dir, uint32_t l, uint64_t s,
     return p;
 }
 
-int plan_run(tft_plan *p, void *x, hipStream_t st) {
+// Optional per-launch event pairs, for timing the leaf kernels on their stream.
+struct LaunchTimer {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    ~LaunchTimer() {
+        for (auto &e : ev) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+    }
+    hipError_t mark(hipStream_t st, bool start) {
+        if (start) {
+            ev.emplace_back();
+            hipError_t e = hipEventCreate(&ev.back().first);
+            if (e == hipSuccess) e = hipEventCreate(&ev.back().second);
+            if (e != hipSuccess) return e;
+            return hipEventRecord(ev.back().first, st);
+        }
+        return hipEventRecord(ev.back().second, st);
+    }
+    float total_ms() {
+        float t = 0;
+        for (auto &e : ev) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) t += ms;
+        }
+        return t;
+    }
+};
+
+int plan_run(tft_plan *p, void *x, hipStream_t st, LaunchTimer *lt = nullptr) {
     std::lock_guard<std::mutex> lk(p->mu);
     int rc = plan_upload(p);
     if (rc) return rc;
@@ -167,7 +196,8 @@ int plan_run(tft_plan *p, void *x, hipStream_t st) {
     const uint32_t ord_mask = ring_ord(&p->ring) - 1;
     for (size_t i = 0; i < p->sched.passes.size(); i++) {
         const PassDesc &pd = p->sched.passes[i];
-        hipError_t e;
+        hipError_t e = hipSuccess;
+        if (lt && (e = lt->mark(st, true)) != hipSuccess) return dev_fail(e, "timer");
         if (p->ring.kind == TFT_RING_FERMAT)
             e = launch_fermat_leaf(p->ring.N / 32, p->nwaves[i], pd.job_count, pd.max_len, p->d_jobs, pd.job_begin,
                                    p->d_progs, p->d_steps, p->d_ops, static_cast<uint32_t *>(x), cap, ord_mask, st);
@@ -176,6 +206,7 @@ int plan_run(tft_plan *p, void *x, hipStream_t st) {
                                  pd.job_begin, p->d_progs, p->d_steps, p->d_ops, static_cast<uint64_t *>(x), ord_mask,
                                  st);
         if (e != hipSuccess) return dev_fail(e, "leaf pass");
+        if (lt && (e = lt->mark(st, false)) != hipSuccess) return dev_fail(e, "timer");
     }
     return TFT_OK;
 }
@@ -376,9 +407,9 @@ int zx_mul_ss_workspace(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32
     return TFT_OK;
 }
 
-int zx_mul_ss(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uint32_t *h, uint64_t len_h,
-              uint32_t h_limbs, uint32_t *out, uint32_t out_limbs, const tft_ss_params *params, void *ws,
-              uint64_t ws_bytes, void *stream) {
+static int ss_run(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uint32_t *h, uint64_t len_h,
+                  uint32_t h_limbs, uint32_t *out, uint32_t out_limbs, const tft_ss_params *params, void *ws,
+                  uint64_t ws_bytes, hipStream_t hs, tft_ss_timing *tm) {
     if (!g || !h || !out) return TFT_E_ARG;
     SSShape sh;
     int st = ss_shape(len_g, g_limbs, len_h, h_limbs, params, &sh);
@@ -386,23 +417,81 @@ int zx_mul_ss(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uint32_
     const uint64_t bits = 32ull * (g_limbs + h_limbs) + log2u(std::min(len_g, len_h));
     if (32ull * out_limbs < bits) return TFT_E_RANGE;
     if (!ws || ws_bytes < sh.ws) return TFT_E_WORKSPACE;
-    hipStream_t hs = static_cast<hipStream_t>(stream);
     tft_ring ring{TFT_RING_FERMAT, sh.N, 0, 0, 0};
     uint32_t *A = static_cast<uint32_t *>(ws);
     uint32_t *B = A + sh.L * (sh.W + 1);
     const tft_split *split = params ? &params->split : nullptr;
-    hipError_t e = launch_fermat_pack(sh.W, g, len_g, g_limbs, A, sh.L, hs);
+    tft_plan *pg = cached_plan(&ring, 0, sh.l, 0, len_g, sh.n, 0, split);
+    tft_plan *ph = cached_plan(&ring, 0, sh.l, 0, len_h, sh.n, 0, split);
+    tft_plan *pi = cached_plan(&ring, 1, sh.l, 0, sh.n, sh.n, 0, split);
+    hipEvent_t ev[7] = {};
+    LaunchTimer lt;
+    LaunchTimer *ltp = tm ? &lt : nullptr;
+    if (tm) {
+        for (auto &e : ev)
+            if (hipEventCreate(&e) != hipSuccess) return dev_fail(hipErrorUnknown, "hipEventCreate");
+    }
+    auto mark = [&](int i) { return tm ? hipEventRecord(ev[i], hs) : hipSuccess; };
+    hipError_t e = mark(0);
+    if (e == hipSuccess) e = launch_fermat_pack(sh.W, g, len_g, g_limbs, A, sh.L, hs);
     if (e == hipSuccess) e = launch_fermat_pack(sh.W, h, len_h, h_limbs, B, sh.L, hs);
-    if (e != hipSuccess) return dev_fail(e, "pack");
-    st = plan_run(cached_plan(&ring, 0, sh.l, 0, len_g, sh.n, 0, split), A, hs);
-    if (st) return st;
-    st = plan_run(cached_plan(&ring, 0, sh.l, 0, len_h, sh.n, 0, split), B, hs);
-    if (st) return st;
-    e = launch_fermat_pointwise(sh.W, sh.n, A, B, A, sh.L, (uint32_t)((2 * sh.N - sh.l) % (2 * sh.N)), hs);
-    if (e != hipSuccess) return dev_fail(e, "pointwise");
-    st = plan_run(cached_plan(&ring, 1, sh.l, 0, sh.n, sh.n, 0, split), A, hs);
-    if (st) return st;
-    return hip_status(launch_fermat_unpack(sh.W, A, sh.L, sh.n, out, out_limbs, hs));
+    if (e == hipSuccess) e = mark(1);
+    if (e != hipSuccess) st = dev_fail(e, "pack");
+    if (!st) st = plan_run(pg, A, hs, ltp);
+    if (!st && (e = mark(2)) != hipSuccess) st = dev_fail(e, "event");
+    if (!st) st = plan_run(ph, B, hs, ltp);
+    if (!st && (e = mark(3)) != hipSuccess) st = dev_fail(e, "event");
+    if (!st) {
+        e = launch_fermat_pointwise(sh.W, sh.n, A, B, A, sh.L, (uint32_t)((2 * sh.N - sh.l) % (2 * sh.N)), hs);
+        if (e == hipSuccess) e = mark(4);
+        if (e != hipSuccess) st = dev_fail(e, "pointwise");
+    }
+    if (!st) st = plan_run(pi, A, hs, ltp);
+    if (!st && (e = mark(5)) != hipSuccess) st = dev_fail(e, "event");
+    if (!st) {
+        e = launch_fermat_unpack(sh.W, A, sh.L, sh.n, out, out_limbs, hs);
+        if (e == hipSuccess) e = mark(6);
+        if (e != hipSuccess) st = dev_fail(e, "unpack");
+    }
+    if (tm) {
+        if (!st) {
+            e = hipEventSynchronize(ev[6]);
+            if (e != hipSuccess) st = dev_fail(e, "hipEventSynchronize");
+        }
+        if (!st) {
+            float ms[6];
+            for (int i = 0; i < 6; i++) (void)hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]);
+            tm->pack_ms = ms[0];
+            tm->tft_g_ms = ms[1];
+            tm->tft_h_ms = ms[2];
+            tm->pointwise_ms = ms[3];
+            tm->itft_ms = ms[4];
+            tm->unpack_ms = ms[5];
+            (void)hipEventElapsedTime(&tm->total_ms, ev[0], ev[6]);
+            tm->leaf_kernel_ms = lt.total_ms();
+            tm->leaf_launches = (uint32_t)lt.ev.size();
+            tm->n = sh.n;
+            tm->l = sh.l;
+            tm->N = sh.N;
+        }
+        for (auto &x : ev) (void)hipEventDestroy(x);
+    }
+    return st;
+}
+
+int zx_mul_ss(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uint32_t *h, uint64_t len_h,
+              uint32_t h_limbs, uint32_t *out, uint32_t out_limbs, const tft_ss_params *params, void *ws,
+              uint64_t ws_bytes, void *stream) {
+    return ss_run(g, len_g, g_limbs, h, len_h, h_limbs, out, out_limbs, params, ws, ws_bytes,
+                  static_cast<hipStream_t>(stream), nullptr);
+}
+
+int zx_mul_ss_timed(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uint32_t *h, uint64_t len_h,
+                    uint32_t h_limbs, uint32_t *out, uint32_t out_limbs, const tft_ss_params *params, void *ws,
+                    uint64_t ws_bytes, void *stream, tft_ss_timing *timing) {
+    if (!timing) return TFT_E_ARG;
+    return ss_run(g, len_g, g_limbs, h, len_h, h_limbs, out, out_limbs, params, ws, ws_bytes,
+                  static_cast<hipStream_t>(stream), timing);
 }
 
 // ---------------------------------------------------------------------------
