@@ -72,7 +72,9 @@ typedef struct {
 /* Split policy for the Bailey decomposition (Sect. 2: L = L1 L2).
  * top_l1     log2 of L1 at the top level; 0 = the paper's floor(l/2) (Alg. 1, Alg. 2).
  * leaf_log2  log2 of the largest sub-transform run inside one workgroup's LDS;
- *            0 = the largest that fits.  Every split gives identical outputs. */
+ *            0 = the largest that fits.  A larger value is accepted for planning
+ *            (tft_plan_export) but tft_plan_execute then returns TFT_E_UNSUPPORTED.
+ *            Every split gives identical outputs. */
 typedef struct {
     uint32_t top_l1;
     uint32_t leaf_log2;

@@ -65,7 +65,7 @@ uint32_t ring_ord(const tft_ring *r) { return r->kind == TFT_RING_FERMAT ? 2u * 
 
 // LDS bytes of one cell inside a leaf workgroup
 uint64_t cell_lds_bytes(const tft_ring *r) {
-    return r->kind == TFT_RING_FERMAT ? 4ull * (r->N / 32 + 1) : 8ull * r->K;
+    return r->kind == TFT_RING_FERMAT ? fermat_lds_cell_bytes(r->N / 32) : 8ull * r->K;
 }
 
 uint32_t max_leaf_log2(const tft_ring *r) {
@@ -146,8 +146,10 @@ tft_plan *plan_build(const tft_ring *ring, uint32_t dir, uint32_t l, uint64_t s,
     p->z = z;
     p->n = n;
     p->f = dir ? f : 0;
+    // an explicit leaf size is honoured as given (a plan is host data); plans whose
+    // leaves exceed the LDS budget are refused when executed
     uint32_t leaf = max_leaf_log2(ring);
-    if (split && split->leaf_log2) leaf = std::min(leaf, std::max<uint32_t>(1, split->leaf_log2));
+    if (split && split->leaf_log2) leaf = std::min<uint32_t>(11, split->leaf_log2);
     uint32_t top = (split && split->top_l1 && split->top_l1 < l) ? split->top_l1 : 0;
     p->sched = build_schedule(dir, l, ring_ord(ring), p->s, z, n, p->f, leaf, top);
     const uint32_t seg = ring->kind == TFT_RING_FERMAT ? std::min<uint32_t>(ring->N / 32, 64) : 64;
@@ -160,29 +162,46 @@ tft_plan *plan_build(const tft_ring *ring, uint32_t dir, uint32_t l, uint64_t s,
 }
 
 // Optional per-launch event pairs, for timing the leaf kernels on their stream.
+// Event pairs are created up front (reserve) so that timing adds only the
+// event records between launches.
 struct LaunchTimer {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t used = 0;
     ~LaunchTimer() {
         for (auto &e : ev) {
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
         }
     }
+    hipError_t reserve(size_t n) {
+        while (ev.size() < n) {
+            std::pair<hipEvent_t, hipEvent_t> p;
+            hipError_t e = hipEventCreate(&p.first);
+            if (e != hipSuccess) return e;
+            e = hipEventCreate(&p.second);
+            if (e != hipSuccess) {
+                (void)hipEventDestroy(p.first);
+                return e;
+            }
+            ev.push_back(p);
+        }
+        return hipSuccess;
+    }
     hipError_t mark(hipStream_t st, bool start) {
         if (start) {
-            ev.emplace_back();
-            hipError_t e = hipEventCreate(&ev.back().first);
-            if (e == hipSuccess) e = hipEventCreate(&ev.back().second);
-            if (e != hipSuccess) return e;
-            return hipEventRecord(ev.back().first, st);
+            if (used == ev.size()) {
+                hipError_t e = reserve(used + 1);
+                if (e != hipSuccess) return e;
+            }
+            return hipEventRecord(ev[used++].first, st);
         }
-        return hipEventRecord(ev.back().second, st);
+        return hipEventRecord(ev[used - 1].second, st);
     }
     float total_ms() {
         float t = 0;
-        for (auto &e : ev) {
+        for (size_t i = 0; i < used; i++) {
             float ms = 0;
-            if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) t += ms;
+            if (hipEventElapsedTime(&ms, ev[i].first, ev[i].second) == hipSuccess) t += ms;
         }
         return t;
     }
@@ -190,6 +209,8 @@ struct LaunchTimer {
 
 int plan_run(tft_plan *p, void *x, hipStream_t st, LaunchTimer *lt = nullptr) {
     std::lock_guard<std::mutex> lk(p->mu);
+    for (const PassDesc &pd : p->sched.passes)
+        if ((uint64_t)pd.max_len * cell_lds_bytes(&p->ring) > lds_budget_bytes()) return TFT_E_UNSUPPORTED;
     int rc = plan_upload(p);
     if (rc) return rc;
     const uint64_t cap = 1ull << p->l;
@@ -430,6 +451,8 @@ static int ss_run(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uin
     if (tm) {
         for (auto &e : ev)
             if (hipEventCreate(&e) != hipSuccess) return dev_fail(hipErrorUnknown, "hipEventCreate");
+        hipError_t re = lt.reserve(pg->sched.passes.size() + ph->sched.passes.size() + pi->sched.passes.size());
+        if (re != hipSuccess) return dev_fail(re, "hipEventCreate");
     }
     auto mark = [&](int i) { return tm ? hipEventRecord(ev[i], hs) : hipSuccess; };
     hipError_t e = mark(0);
@@ -469,7 +492,7 @@ static int ss_run(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uin
             tm->unpack_ms = ms[5];
             (void)hipEventElapsedTime(&tm->total_ms, ev[0], ev[6]);
             tm->leaf_kernel_ms = lt.total_ms();
-            tm->leaf_launches = (uint32_t)lt.ev.size();
+            tm->leaf_launches = (uint32_t)lt.used;
             tm->n = sh.n;
             tm->l = sh.l;
             tm->N = sh.N;

@@ -12,22 +12,65 @@ namespace tft {
 namespace {
 
 constexpr uint32_t kLdsBudget = 160u * 1024u;
+constexpr uint32_t kLeafStaticLds = 0u;  // no static LDS in fermat_leaf_kernel
 
-// Copy leaf cells [0, n) between the global array and LDS.
-template <int W, bool IN>
+// Copy leaf cells [0, n) between the global array (cell-contiguous limbs) and
+// LDS (cells ESZ dwords apart, limb k at F::addr(k)).  Each thread keeps
+// CB 16-byte global accesses in flight before touching LDS.
+constexpr int CB = 8;
+
+template <class F, bool IN>
 __device__ __forceinline__ void copy_cells(uint32_t *sm, uint32_t *x, const Job &J, uint32_t n, uint32_t tid,
                                            uint32_t nthr) {
+    constexpr int W = F::W;
     if constexpr (W % 4 == 0) {
         constexpr uint32_t WQ = W / 4;
         const uint32_t total = n * WQ;
-        for (uint32_t q = tid; q < total; q += nthr) {
-            const uint32_t cell = q / WQ, off = q % WQ;
-            uint4 *g = reinterpret_cast<uint4 *>(x + (J.base + (uint64_t)cell * J.stride) * W) + off;
-            uint4 *s = reinterpret_cast<uint4 *>(sm) + q;
-            if (IN)
-                *s = *g;
-            else
-                *g = *s;
+        for (uint32_t q0 = tid; q0 < total; q0 += nthr * CB) {
+            uint4 v[CB];
+            if (IN) {
+#pragma unroll
+                for (int b = 0; b < CB; ++b) {
+                    const uint32_t q = q0 + b * nthr;
+                    if (q < total) {
+                        const uint32_t cell = q / WQ, off = q % WQ;
+                        v[b] = reinterpret_cast<const uint4 *>(x + (J.base + (uint64_t)cell * J.stride) * W)[off];
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < CB; ++b) {
+                    const uint32_t q = q0 + b * nthr;
+                    if (q < total) {
+                        const uint32_t cell = q / WQ, k = (q % WQ) * 4u;
+                        uint32_t *s = sm + cell * F::ESZ;
+                        s[F::addr(k)] = v[b].x;
+                        s[F::addr(k + 1)] = v[b].y;
+                        s[F::addr(k + 2)] = v[b].z;
+                        s[F::addr(k + 3)] = v[b].w;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int b = 0; b < CB; ++b) {
+                    const uint32_t q = q0 + b * nthr;
+                    if (q < total) {
+                        const uint32_t cell = q / WQ, k = (q % WQ) * 4u;
+                        const uint32_t *s = sm + cell * F::ESZ;
+                        v[b].x = s[F::addr(k)];
+                        v[b].y = s[F::addr(k + 1)];
+                        v[b].z = s[F::addr(k + 2)];
+                        v[b].w = s[F::addr(k + 3)];
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < CB; ++b) {
+                    const uint32_t q = q0 + b * nthr;
+                    if (q < total) {
+                        const uint32_t cell = q / WQ, off = q % WQ;
+                        reinterpret_cast<uint4 *>(x + (J.base + (uint64_t)cell * J.stride) * W)[off] = v[b];
+                    }
+                }
+            }
         }
     } else {
         const uint32_t total = n * W;
@@ -35,30 +78,30 @@ __device__ __forceinline__ void copy_cells(uint32_t *sm, uint32_t *x, const Job 
             const uint32_t cell = q / W, off = q % W;
             uint32_t *g = x + (J.base + (uint64_t)cell * J.stride) * W + off;
             if (IN)
-                sm[q] = *g;
+                sm[cell * F::ESZ + F::addr(off)] = *g;
             else
-                *g = sm[q];
+                *g = sm[cell * F::ESZ + F::addr(off)];
         }
     }
 }
 
-template <int S, int R>
+template <int S, int C>
 __global__ void __launch_bounds__(512) fermat_leaf_kernel(const Job *__restrict__ jobs,
                                                            const LeafProg *__restrict__ progs,
                                                            const LeafStep *__restrict__ steps,
                                                            const LeafOp *__restrict__ ops, uint32_t *__restrict__ x,
                                                            uint64_t cap, uint32_t ord_mask, uint32_t lds_cells,
                                                            uint32_t job_offset) {
-    using F = FermatSeg<S, R>;
-    constexpr int W = S * R;
+    using F = FChunk<S, C>;
+    constexpr int W = F::W;
     constexpr uint32_t G = 64 / S;
     extern __shared__ uint32_t sm[];
-    uint32_t *stop = sm + (size_t)lds_cells * W;
+    uint32_t *stop = sm + (size_t)lds_cells * F::ESZ;
     const Job J = jobs[job_offset + blockIdx.x];
     const LeafProg P = progs[J.prog];
     const uint32_t tid = threadIdx.x, nthr = blockDim.x;
 
-    copy_cells<W, true>(sm, x, J, J.nload, tid, nthr);
+    copy_cells<F, true>(sm, x, J, J.nload, tid, nthr);
     for (uint32_t t = tid; t < J.nload; t += nthr) stop[t] = x[cap * W + J.base + (uint64_t)t * J.stride];
     __syncthreads();
 
@@ -75,7 +118,7 @@ __global__ void __launch_bounds__(512) fermat_leaf_kernel(const Job *__restrict_
                 const uint32_t i0 = (o.w0 >> 4) & 16383u, i1 = (o.w0 >> 18) & 16383u;
                 const uint32_t e =
                     (uint32_t)((((uint64_t)J.s << (o.w1 >> 24)) + (uint64_t)(o.w1 & 0xFFFFFFu)) & ord_mask);
-                uint32_t *x0 = sm + i0 * W, *x1 = sm + i1 * W;
+                uint32_t *x0 = sm + i0 * F::ESZ, *x1 = sm + i1 * F::ESZ;
                 uint32_t *t0 = stop + i0, *t1 = stop + i1;
                 switch (code) {
                     case OP_T22: B.t22(x0, x1, t0, t1, e); break;
@@ -98,7 +141,7 @@ __global__ void __launch_bounds__(512) fermat_leaf_kernel(const Job *__restrict_
         __syncthreads();
     }
 
-    copy_cells<W, false>(sm, x, J, J.nstore, tid, nthr);
+    copy_cells<F, false>(sm, x, J, J.nstore, tid, nthr);
     for (uint32_t t = tid; t < J.nstore; t += nthr) x[cap * W + J.base + (uint64_t)t * J.stride] = stop[t];
 }
 
@@ -123,17 +166,17 @@ constexpr uint32_t pw_threads(int W) {
     return (t + 63) / 64 * 64;
 }
 
-template <int S, int R>
+template <int S, int C>
 __global__ void __launch_bounds__(256) fermat_pointwise_kernel(const uint32_t *__restrict__ a,
                                                                const uint32_t *__restrict__ b, uint32_t *c,
                                                                uint64_t cap, uint32_t scale_e) {
-    using F = FermatSeg<S, R>;
-    constexpr int W = S * R;
+    using F = FChunk<S, C>;
+    constexpr int W = F::W;
     extern __shared__ uint32_t sm[];
     uint32_t *A = sm, *Bv = A + W;
     uint32_t *P0 = Bv + W, *P1 = P0 + W, *P2 = P1 + W, *N0 = P2 + W, *N1 = N0 + W, *N2 = N1 + W;
-    uint32_t *Y = N2 + W;
-    uint32_t &topY = Y[W];
+    uint32_t *Y = N2 + W;  // F::ESZ dwords, LDS layout of one element
+    uint32_t &topY = Y[F::ESZ];
     const uint64_t i = blockIdx.x;
     const uint32_t tid = threadIdx.x, nthr = blockDim.x;
 
@@ -232,38 +275,44 @@ __global__ void __launch_bounds__(256) fermat_pointwise_kernel(const uint32_t *_
 
     if (tid < 64) {
         const FermatOps<F> Bo;
-        const bool active = (Bo.lane < (uint32_t)S);  // segment 0 only
-        if (active) {
+        if (Bo.lane < (uint32_t)S) {  // segment 0 only
+            uint32_t s3[C];
+            uint32_t top;
             if (!special) {
-                uint64_t c1 = 0, c2 = 0, c3 = 0;
-                for (int r = 0; r < R; ++r) {
-                    const uint32_t k = (uint32_t)r * S + Bo.l;
-                    const uint32_t hp = k ? P0[k - 1] : N0[W - 1];
-                    const uint32_t hn = k ? N0[k - 1] : P0[W - 1];
-                    uint32_t v = Bo.add_row(A[k], hp, c1);
-                    v = Bo.sub_row(v, Bv[k], c2);
-                    v = Bo.sub_row(v, hn, c3);
-                    Y[k] = v;
+                uint32_t pl[C], hp[C], nl[C], hn[C], s1[C], s2[C];
+#pragma unroll
+                for (int j = 0; j < C; ++j) {
+                    const uint32_t k = Bo.l * C + j;
+                    pl[j] = A[k];
+                    nl[j] = Bv[k];
+                    hp[j] = k ? P0[k - 1] : N0[W - 1];
+                    hn[j] = k ? N0[k - 1] : P0[W - 1];
                 }
-                Bo.canon(Y, &topY, (int)Bo.seg_bit(c1) - (int)Bo.seg_bit(c2) - (int)Bo.seg_bit(c3), 0, 0u);
+                const uint32_t c1 = Bo.add(s1, pl, hp);
+                const uint32_t b2 = Bo.sub(s2, s1, nl);
+                const uint32_t b3 = Bo.sub(s3, s2, hn);
+                top = Bo.canon(s3, (int)c1 - (int)b2 - (int)b3, 0, 0u);
             } else if (ta && tb) {
                 // (-1)(-1) = 1
-                for (int r = 0; r < R; ++r) Y[(uint32_t)r * S + Bo.l] = 0u;
-                Bo.canon(Y, &topY, -1, 0, 0u);
+#pragma unroll
+                for (int j = 0; j < C; ++j) s3[j] = 0u;
+                top = Bo.canon(s3, -1, 0, 0u);
             } else {
-                // (-1) * v = 2^N + 1 - v = ~v + 2
+                // (-1) v = 2^N + 1 - v = ~v + 2
                 const uint32_t *v = ta ? Bv : A;
-                for (int r = 0; r < R; ++r) {
-                    const uint32_t k = (uint32_t)r * S + Bo.l;
-                    Y[k] = ~v[k];
-                }
-                Bo.canon(Y, &topY, -2, 0, 0u);
+#pragma unroll
+                for (int j = 0; j < C; ++j) s3[j] = ~v[Bo.l * C + j];
+                top = Bo.canon(s3, -2, 0, 0u);
             }
-            if (scale_e) Bo.scale(Y, &topY, scale_e);
+            Bo.st(Y, s3);
+            if (scale_e)
+                Bo.twist_store(Y, &topY, scale_e, (int)top);
+            else if (Bo.l == 0u)
+                topY = top;
         }
     }
     __syncthreads();
-    for (uint32_t q = tid; q < (uint32_t)W; q += nthr) c[i * W + q] = Y[q];
+    for (uint32_t q = tid; q < (uint32_t)W; q += nthr) c[i * W + q] = Y[F::addr(q)];
     if (tid == 0) c[cap * W + i] = topY;
 }
 
@@ -290,47 +339,53 @@ __global__ void fermat_unpack_kernel(const uint32_t *__restrict__ x, uint64_t ca
     }
 }
 
-template <int S, int R>
+template <int S, int C>
 hipError_t leaf_launch(uint32_t nwaves, uint32_t njobs, uint32_t lds_cells, const Job *jobs, uint32_t job_offset,
                        const LeafProg *progs, const LeafStep *steps, const LeafOp *ops, uint32_t *x, uint64_t cap,
                        uint32_t ord_mask, hipStream_t st) {
-    constexpr int W = S * R;
-    const size_t lds = (size_t)lds_cells * (W + 1) * 4;
-    if (lds > kLdsBudget) return hipErrorInvalidValue;
+    const size_t lds = (size_t)lds_cells * (FChunk<S, C>::ESZ + 1) * 4;
+    if (lds > kLdsBudget - kLeafStaticLds) return hipErrorInvalidValue;
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fermat_leaf_kernel<S, R>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fermat_leaf_kernel<S, C>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)(kLdsBudget - kLeafStaticLds));
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL((fermat_leaf_kernel<S, R>), dim3(njobs), dim3(64 * nwaves), lds, st, jobs, progs, steps, ops,
+    hipLaunchKernelGGL((fermat_leaf_kernel<S, C>), dim3(njobs), dim3(64 * nwaves), lds, st, jobs, progs, steps, ops,
                        x, cap, ord_mask, lds_cells, job_offset);
     return hipGetLastError();
 }
 
-template <int S, int R>
+template <int S, int C>
 hipError_t pointwise_launch(uint64_t n, const uint32_t *a, const uint32_t *b, uint32_t *c, uint64_t cap,
                             uint32_t scale_e, hipStream_t st) {
-    constexpr int W = S * R;
-    const size_t lds = (size_t)(9 * W + 1) * 4;
+    constexpr int W = S * C;
+    const size_t lds = (size_t)(8 * W + FChunk<S, C>::ESZ + 1) * 4;
     if (lds > kLdsBudget) return hipErrorInvalidValue;
     static bool attr = false;
     if (!attr && lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fermat_pointwise_kernel<S, R>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fermat_pointwise_kernel<S, C>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
         if (e != hipSuccess) return e;
         attr = true;
     }
     const uint32_t thr = pw_threads(W);
-    hipLaunchKernelGGL((fermat_pointwise_kernel<S, R>), dim3((uint32_t)n), dim3(thr), lds, st, a, b, c, cap,
+    hipLaunchKernelGGL((fermat_pointwise_kernel<S, C>), dim3((uint32_t)n), dim3(thr), lds, st, a, b, c, cap,
                        scale_e);
     return hipGetLastError();
 }
 
 }  // namespace
 
-uint32_t lds_budget_bytes() { return kLdsBudget; }
+uint32_t lds_budget_bytes() { return kLdsBudget - kLeafStaticLds; }
+
+uint32_t fermat_lds_cell_bytes(uint32_t W) {
+    const uint32_t S = W < 64 ? W : 64, C = W / S;
+    const uint32_t CP = C > 1 ? C + 1 : 1;
+    return 4u * (S * CP + 1u);
+}
 
 #define TFT_FERMAT_DISPATCH(W, FN, ...)                      \
     switch (W) {                                             \

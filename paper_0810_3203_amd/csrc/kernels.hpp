@@ -27,4 +27,7 @@ hipError_t launch_fermat_unpack(uint32_t W, const uint32_t *x, uint64_t cap, uin
 // Largest LDS bytes one workgroup may use.
 uint32_t lds_budget_bytes();
 
+// LDS bytes of one Fermat cell inside a leaf workgroup (padded chunk layout plus top word).
+uint32_t fermat_lds_cell_bytes(uint32_t W);
+
 }  // namespace tft
