@@ -122,14 +122,20 @@ int itft_inverse(const tft_ring *ring, uint32_t l, uint64_t s, uint64_t z, uint6
 int pointwise_mul(const tft_ring *ring, uint64_t n, const void *a, const void *b, void *c, uint64_t cap,
                   uint32_t scale_log2, void *stream);
 
-/* Parameters of a Schoenhage-Strassen product; NULL means the defaults.
- *   N      ring Z/(2^N+1); 0 = smallest supported N holding every output coefficient.
- *   l      transform length 2^l; 0 = smallest with 2^l >= len_g + len_h - 1.
- *   split  Bailey split policy (top_l1 = leaf_log2 = 0: paper split, largest leaf). */
+/* Parameters of a Schoenhage-Strassen product; NULL (or all zero) means the defaults.
+ *   N      ring Z/(2^N+1); 0 = the smallest supported N that holds a product cell.
+ *   l      transform length 2^l; 0 = smallest with 2^l >= cells of g + cells of h - 1.
+ *   split  Bailey split policy (top_l1 = leaf_log2 = 0: paper split, largest leaf).
+ *   k      coefficients per ring element (0 or 1: one, as in Sect. 5.1).  With k > 1
+ *          coefficient e*k+j of an operand sits in slot j (ws limbs, ws = the output
+ *          coefficient bound in limbs) of cell e; a product cell holds 2k-1 slots
+ *          (N >= 32 (2k-1) ws) and an output coefficient is the sum of two
+ *          overlapping slots.  Results are identical for every k. */
 typedef struct {
     uint32_t N;
     uint32_t l;
     tft_split split;
+    uint32_t k;
 } tft_ss_params;
 
 /* Workspace bytes zx_mul_ss needs for these operand shapes and parameters. */
@@ -179,6 +185,118 @@ int zmx_mul_nussbaumer_workspace(uint64_t len_g, uint64_t len_h, uint32_t log2K,
  *   out    len_g + len_h - 1 coefficients (uint64, in [0, m)). */
 int zmx_mul_nussbaumer(const uint64_t *g, uint64_t len_g, const uint64_t *h, uint64_t len_h, uint64_t m,
                        uint32_t log2K, uint64_t *out, void *ws, uint64_t ws_bytes, void *stream);
+
+/* ---- batches of independent Z[x] products ---- */
+
+/* One Schoenhage-Strassen product of a batch (device pointers, as in zx_mul_ss). */
+typedef struct {
+    const uint32_t *g;
+    uint64_t len_g;
+    uint32_t g_limbs;
+    const uint32_t *h;
+    uint64_t len_h;
+    uint32_t h_limbs;
+    uint32_t *out;
+    uint32_t out_limbs;
+    tft_ss_params params; /* all zero: the defaults of zx_mul_ss */
+} tft_zx_request;
+
+typedef struct tft_batch_plan tft_batch_plan;
+
+/* Plan `count` products for execution together (host work only).  Requests are
+ * grouped by ring size; in each group pass p of every TFT (resp. ITFT) is one
+ * kernel launch, and the pointwise products are one launch.  Requests whose
+ * arguments are invalid are skipped and reported by tft_batch_plan_status.
+ * max_workspace (bytes, 0 = no limit) splits the requests into consecutive
+ * chunks run one after another in the same workspace; a request whose own
+ * workspace, rounded up to a multiple of 256 bytes, exceeds the limit is
+ * skipped with TFT_E_WORKSPACE.  The request pointers are used by every
+ * execution of the plan. */
+int tft_batch_plan_create(const tft_zx_request *reqs, uint32_t count, uint64_t max_workspace,
+                          tft_batch_plan **plan);
+
+/* Device workspace bytes the plan needs. */
+uint64_t tft_batch_plan_workspace(const tft_batch_plan *plan);
+
+/* Per-request status (count entries): TFT_OK, or why the request was skipped. */
+int tft_batch_plan_status(const tft_batch_plan *plan, int *status);
+
+/* Kernel launches of one execution. */
+uint32_t tft_batch_plan_launches(const tft_batch_plan *plan);
+
+/* Run every planned product on `stream`.  use_graph = 0: the launches are
+ * issued directly.  use_graph = 1: the first call (and any call with another
+ * workspace pointer) runs the launches and captures them into a hipGraph;
+ * later calls replay the graph.  The first call uploads the plan's descriptors
+ * (hipMalloc); nothing is allocated afterwards. */
+int tft_batch_plan_execute(tft_batch_plan *plan, void *ws, uint64_t ws_bytes, int use_graph, void *stream);
+
+/* Free a batch plan (host data, device descriptors, graph).  NULL is ignored. */
+void tft_batch_plan_destroy(tft_batch_plan *plan);
+
+/* ---- choosing the parameters of a product (not part of the paper) ----
+ * A candidate fixes the bundling factor k (then N and l are the smallest the
+ * product allows) and the top split of Alg. 1/2.  Every candidate gives the
+ * same output bits; only the time differs. */
+
+#define TFT_SS_FEATURES 12
+
+/* The candidate set of a product shape, in a fixed order: k = 1, 2, 4, ..., 32
+ * (those the ring sizes allow), each with the paper's split and, when the
+ * transform needs more than one leaf, a split whose column pass is one leaf.
+ * out == NULL: only *count is set.  TFT_E_ARG if cap < *count. */
+int tft_ss_candidates(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h_limbs, tft_ss_params *out,
+                      uint32_t cap, uint32_t *count);
+
+/* The fixed default rule: the smallest k whose cell-array footprint is within
+ * 5/4 of the smallest footprint over the candidate k, with the paper's split. */
+int tft_ss_default_params(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h_limbs,
+                          tft_ss_params *out);
+
+/* TFT_SS_FEATURES scaled features of (product shape, candidate) read by the
+ * cost model: operand lengths and limbs, k, l, ring size, fill n/L,
+ * footprint, pointwise limb products, transform pass bytes, pass count,
+ * top split share.  Host work only. */
+int tft_ss_features(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h_limbs, const tft_ss_params *p,
+                    float *feat);
+
+/* Exhaustive timing of ncand candidates on one request (device buffers; its
+ * out is written): per candidate one untimed run, then `reps` runs each
+ * bracketed by HIP events on `stream`; ms[c] = median.  *best (if not NULL) =
+ * index of the smallest time, ties to the smaller index.  ws must hold the
+ * largest candidate's zx_mul_ss_workspace. */
+int tft_ss_time(const tft_zx_request *req, const tft_ss_params *cands, uint32_t ncand, uint32_t reps, void *ws,
+                uint64_t ws_bytes, void *stream, float *ms, uint32_t *best);
+
+/* fp32 multilayer perceptron predicting log run time from the features:
+ * in_features -> `depth` ReLU layers of `hidden` units -> 1 output.  Forward,
+ * backward (mean squared error) and Adam run as HIP kernels.  Parameters are
+ * one float array: per layer the weights (out x in, row-major) then the
+ * biases; initialised He-uniform from `seed` (SplitMix64), biases zero. */
+typedef struct tft_mlp tft_mlp;
+
+int tft_mlp_create(uint32_t in_features, uint32_t hidden, uint32_t depth, uint64_t seed, tft_mlp **mlp);
+uint64_t tft_mlp_param_count(const tft_mlp *mlp);
+/* Copy the n = tft_mlp_param_count parameters to / from host memory. */
+int tft_mlp_get_params(const tft_mlp *mlp, float *host, uint64_t n);
+int tft_mlp_set_params(tft_mlp *mlp, const float *host, uint64_t n);
+/* y[b] = model(x[b]) for `batch` rows; x (batch x in_features) and y are device buffers. */
+int tft_mlp_forward(tft_mlp *mlp, const float *x, uint32_t batch, float *y, void *stream);
+/* Gradient of loss = sum_b (model(x_b) - target_b)^2 / (2 batch) with respect to
+ * the parameters (device buffer of param_count floats, may be NULL), and the
+ * loss (device float, may be NULL).  Device buffers throughout. */
+int tft_mlp_gradient(tft_mlp *mlp, const float *x, const float *target, uint32_t batch, float *grad,
+                     float *loss, void *stream);
+/* `iters` full-batch Adam steps (beta1 0.9, beta2 0.999, eps 1e-8) at rate lr;
+ * *final_loss (host, may be NULL) receives the loss after the last step. */
+int tft_mlp_train(tft_mlp *mlp, const float *x, const float *target, uint32_t batch, uint32_t iters, float lr,
+                  float *final_loss, void *stream);
+void tft_mlp_destroy(tft_mlp *mlp);
+
+/* For every request (host array), evaluate the model on all its candidates
+ * and store the candidate of smallest predicted time in reqs[i].params
+ * (ties to the earlier candidate). */
+int tft_mlp_choose_ss(tft_mlp *mlp, tft_zx_request *reqs, uint32_t count, void *stream);
 
 /* ---- explicit plans: transforms with a chosen split, built ahead of use ---- */
 

@@ -8,7 +8,10 @@ it raises instead of falling back to anything else.
 
 from ._binding import (  # noqa: F401
     FERMAT,
+    MLP,
     NEGA,
+    SS_FEATURES,
+    BatchPlan,
     Plan,
     SSParams,
     Split,
@@ -21,7 +24,12 @@ from ._binding import (  # noqa: F401
     lib_path,
     nega_ring,
     pointwise_mul,
+    requests_array,
     ring_check,
+    ss_candidates,
+    ss_default_params,
+    ss_features,
+    ss_time,
     status_string,
     tft_forward,
     zmx_mul_nussbaumer,
@@ -29,10 +37,14 @@ from ._binding import (  # noqa: F401
     zx_mul_ss,
     zx_mul_ss_timed,
     zx_mul_ss_workspace,
+    zx_request,
+    ZXRequest,
 )
 
 __all__ = [
     "FERMAT", "NEGA", "Plan", "SSParams", "Split", "TFTError", "array_bytes", "elem_bytes", "fermat_ring",
     "itft_inverse", "lib", "lib_path", "nega_ring", "pointwise_mul", "ring_check", "status_string", "tft_forward",
     "zmx_mul_nussbaumer", "zmx_mul_nussbaumer_workspace", "zx_mul_ss", "zx_mul_ss_timed", "zx_mul_ss_workspace",
+    "BatchPlan", "MLP", "SS_FEATURES", "ZXRequest", "requests_array", "ss_candidates", "ss_default_params",
+    "ss_features", "ss_time", "zx_request",
 ]

@@ -48,7 +48,16 @@ class SSTiming(ctypes.Structure):
 
 
 class SSParams(ctypes.Structure):
-    _fields_ = [("N", ctypes.c_uint32), ("l", ctypes.c_uint32), ("split", Split)]
+    _fields_ = [("N", ctypes.c_uint32), ("l", ctypes.c_uint32), ("split", Split), ("k", ctypes.c_uint32)]
+
+
+class ZXRequest(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_void_p), ("len_g", ctypes.c_uint64), ("g_limbs", ctypes.c_uint32),
+                ("h", ctypes.c_void_p), ("len_h", ctypes.c_uint64), ("h_limbs", ctypes.c_uint32),
+                ("out", ctypes.c_void_p), ("out_limbs", ctypes.c_uint32), ("params", SSParams)]
+
+
+SS_FEATURES = 12
 
 
 def fermat_ring(N: int) -> Ring:
@@ -109,6 +118,47 @@ def lib():
         L.tft_plan_base_cases.restype = U64
         L.tft_plan_export.argtypes = [P, P, U64, ctypes.POINTER(U64)]
         L.tft_plan_export.restype = I
+        RQ = ctypes.POINTER(ZXRequest)
+        SP = ctypes.POINTER(SSParams)
+        FP = ctypes.POINTER(ctypes.c_float)
+        L.tft_batch_plan_create.argtypes = [RQ, U32, U64, ctypes.POINTER(P)]
+        L.tft_batch_plan_create.restype = I
+        L.tft_batch_plan_workspace.argtypes = [P]
+        L.tft_batch_plan_workspace.restype = U64
+        L.tft_batch_plan_status.argtypes = [P, ctypes.POINTER(I)]
+        L.tft_batch_plan_status.restype = I
+        L.tft_batch_plan_launches.argtypes = [P]
+        L.tft_batch_plan_launches.restype = U32
+        L.tft_batch_plan_execute.argtypes = [P, P, U64, I, P]
+        L.tft_batch_plan_execute.restype = I
+        L.tft_batch_plan_destroy.argtypes = [P]
+        L.tft_batch_plan_destroy.restype = None
+        L.tft_ss_candidates.argtypes = [U64, U32, U64, U32, SP, U32, ctypes.POINTER(U32)]
+        L.tft_ss_candidates.restype = I
+        L.tft_ss_default_params.argtypes = [U64, U32, U64, U32, SP]
+        L.tft_ss_default_params.restype = I
+        L.tft_ss_features.argtypes = [U64, U32, U64, U32, SP, FP]
+        L.tft_ss_features.restype = I
+        L.tft_ss_time.argtypes = [RQ, SP, U32, U32, P, U64, P, FP, ctypes.POINTER(U32)]
+        L.tft_ss_time.restype = I
+        L.tft_mlp_create.argtypes = [U32, U32, U32, U64, ctypes.POINTER(P)]
+        L.tft_mlp_create.restype = I
+        L.tft_mlp_param_count.argtypes = [P]
+        L.tft_mlp_param_count.restype = U64
+        L.tft_mlp_get_params.argtypes = [P, FP, U64]
+        L.tft_mlp_get_params.restype = I
+        L.tft_mlp_set_params.argtypes = [P, FP, U64]
+        L.tft_mlp_set_params.restype = I
+        L.tft_mlp_forward.argtypes = [P, P, U32, P, P]
+        L.tft_mlp_forward.restype = I
+        L.tft_mlp_gradient.argtypes = [P, P, P, U32, P, P, P]
+        L.tft_mlp_gradient.restype = I
+        L.tft_mlp_train.argtypes = [P, P, P, U32, U32, ctypes.c_float, FP, P]
+        L.tft_mlp_train.restype = I
+        L.tft_mlp_destroy.argtypes = [P]
+        L.tft_mlp_destroy.restype = None
+        L.tft_mlp_choose_ss.argtypes = [P, RQ, U32, P]
+        L.tft_mlp_choose_ss.restype = I
         _lib = L
     return _lib
 
@@ -261,6 +311,146 @@ class Plan:
     def close(self):
         if self._p:
             lib().tft_plan_destroy(self._p)
+            self._p = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def zx_request(g, h, out, params=None) -> ZXRequest:
+    """A batch request over device tensors g (len_g, g_limbs), h, out (as in zx_mul_ss)."""
+    r = ZXRequest(g.data_ptr(), g.shape[0], g.shape[1], h.data_ptr(), h.shape[0], h.shape[1],
+                  out.data_ptr(), out.shape[1])
+    if params is not None:
+        r.params = params
+    return r
+
+
+def requests_array(reqs):
+    arr = (ZXRequest * len(reqs))()
+    for i, r in enumerate(reqs):
+        arr[i] = r
+    return arr
+
+
+class BatchPlan:
+    """tft_batch_plan_*: many Z[x] products planned and run together."""
+
+    def __init__(self, reqs, max_workspace=0):
+        self.count = len(reqs)
+        self._reqs = reqs if isinstance(reqs, ctypes.Array) else requests_array(reqs)
+        self._p = ctypes.c_void_p()
+        _check(lib().tft_batch_plan_create(self._reqs, self.count, max_workspace, ctypes.byref(self._p)),
+               "tft_batch_plan_create")
+
+    @property
+    def workspace(self) -> int:
+        return lib().tft_batch_plan_workspace(self._p)
+
+    @property
+    def launches(self) -> int:
+        return lib().tft_batch_plan_launches(self._p)
+
+    def status(self):
+        st = (ctypes.c_int * max(1, self.count))()
+        _check(lib().tft_batch_plan_status(self._p, st), "tft_batch_plan_status")
+        return list(st)[:self.count]
+
+    def execute(self, ws, use_graph=False, stream=None):
+        _check(lib().tft_batch_plan_execute(self._p, _ptr(ws), ws.numel() * ws.element_size() if ws is not None
+                                            else 0, 1 if use_graph else 0, _stream(stream)),
+               "tft_batch_plan_execute")
+
+    def close(self):
+        if self._p:
+            lib().tft_batch_plan_destroy(self._p)
+            self._p = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ss_candidates(len_g, g_limbs, len_h, h_limbs):
+    n = ctypes.c_uint32(0)
+    _check(lib().tft_ss_candidates(len_g, g_limbs, len_h, h_limbs, None, 0, ctypes.byref(n)), "tft_ss_candidates")
+    arr = (SSParams * n.value)()
+    _check(lib().tft_ss_candidates(len_g, g_limbs, len_h, h_limbs, arr, n.value, ctypes.byref(n)),
+           "tft_ss_candidates")
+    return list(arr)
+
+
+def ss_default_params(len_g, g_limbs, len_h, h_limbs) -> SSParams:
+    p = SSParams()
+    _check(lib().tft_ss_default_params(len_g, g_limbs, len_h, h_limbs, ctypes.byref(p)), "tft_ss_default_params")
+    return p
+
+
+def ss_features(len_g, g_limbs, len_h, h_limbs, params):
+    f = (ctypes.c_float * SS_FEATURES)()
+    _check(lib().tft_ss_features(len_g, g_limbs, len_h, h_limbs, ctypes.byref(params), f), "tft_ss_features")
+    return list(f)
+
+
+def ss_time(req, cands, reps, ws, stream=None):
+    """Median ms per candidate and the index of the fastest (tft_ss_time)."""
+    arr = (SSParams * len(cands))(*cands)
+    ms = (ctypes.c_float * len(cands))()
+    best = ctypes.c_uint32(0)
+    _check(lib().tft_ss_time(ctypes.byref(req), arr, len(cands), reps, _ptr(ws), ws.numel() * ws.element_size(),
+                             _stream(stream), ms, ctypes.byref(best)), "tft_ss_time")
+    return list(ms), best.value
+
+
+class MLP:
+    """tft_mlp_*: the fp32 cost model (HIP forward, backward and Adam)."""
+
+    def __init__(self, in_features=SS_FEATURES, hidden=64, depth=3, seed=0):
+        self.in_features = in_features
+        self._p = ctypes.c_void_p()
+        _check(lib().tft_mlp_create(in_features, hidden, depth, seed, ctypes.byref(self._p)), "tft_mlp_create")
+
+    @property
+    def param_count(self) -> int:
+        return lib().tft_mlp_param_count(self._p)
+
+    def get_params(self):
+        n = self.param_count
+        buf = (ctypes.c_float * n)()
+        _check(lib().tft_mlp_get_params(self._p, buf, n), "tft_mlp_get_params")
+        return list(buf)
+
+    def set_params(self, values):
+        n = self.param_count
+        buf = (ctypes.c_float * n)(*values)
+        _check(lib().tft_mlp_set_params(self._p, buf, n), "tft_mlp_set_params")
+
+    def forward(self, x, y, stream=None):
+        _check(lib().tft_mlp_forward(self._p, _ptr(x), x.shape[0], _ptr(y), _stream(stream)), "tft_mlp_forward")
+        return y
+
+    def gradient(self, x, target, grad=None, loss=None, stream=None):
+        _check(lib().tft_mlp_gradient(self._p, _ptr(x), _ptr(target), x.shape[0], _ptr(grad), _ptr(loss),
+                                      _stream(stream)), "tft_mlp_gradient")
+
+    def train(self, x, target, iters, lr, stream=None) -> float:
+        fl = ctypes.c_float(0)
+        _check(lib().tft_mlp_train(self._p, _ptr(x), _ptr(target), x.shape[0], iters, lr, ctypes.byref(fl),
+                                   _stream(stream)), "tft_mlp_train")
+        return fl.value
+
+    def choose(self, reqs, stream=None):
+        """Set reqs[i].params (a ctypes ZXRequest array) to the predicted fastest candidate."""
+        _check(lib().tft_mlp_choose_ss(self._p, reqs, len(reqs), _stream(stream)), "tft_mlp_choose_ss")
+
+    def close(self):
+        if self._p:
+            lib().tft_mlp_destroy(self._p)
             self._p = ctypes.c_void_p()
 
     def __del__(self):

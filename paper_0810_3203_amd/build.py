@@ -18,8 +18,8 @@ LIB = os.path.join(HERE, "libtft.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 ARCH = os.environ.get("TFT_OFFLOAD_ARCH", "gfx950")
 
-DEVICE_SOURCES = ["fermat.hip", "nega.hip"]
-HOST_SOURCES = ["api.cpp", "plan.cpp"]
+DEVICE_SOURCES = ["fermat.hip", "nega.hip", "mlp.hip"]
+HOST_SOURCES = ["api.cpp", "plan.cpp", "batch.cpp", "tune.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
 DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

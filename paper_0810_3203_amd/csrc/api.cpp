@@ -16,6 +16,7 @@
 #include "kernels.hpp"
 #include "nega.hpp"
 #include "plan.hpp"
+#include "ss.hpp"
 
 using namespace tft;
 
@@ -384,47 +385,13 @@ int pointwise_mul(const tft_ring *ring, uint64_t n, const void *a, const void *b
 // Schoenhage-Strassen in Z[x] (Sect. 5.1)
 // ---------------------------------------------------------------------------
 
-struct SSShape {
-    uint32_t N, W, l;
-    uint64_t n, L, ws;
-};
-
-static int ss_shape(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h_limbs, const tft_ss_params *p,
-                    SSShape *o) {
-    if (len_g < 1 || len_h < 1 || g_limbs < 1 || h_limbs < 1) return TFT_E_ARG;
-    const uint64_t n = len_g + len_h - 1;
-    const uint64_t bits = 32ull * (g_limbs + h_limbs) + log2u(std::min(len_g, len_h));
-    uint32_t l = p && p->l ? p->l : std::max<uint32_t>(1, log2u(n));
-    if (l > 24 || (1ull << l) < n) return TFT_E_ARG;
-    const uint64_t L = 1ull << l;
-    uint64_t N;
-    if (p && p->N) {
-        N = p->N;
-        if (N % 32 || !is_pow2(N / 32) || N / 32 > 4096) return TFT_E_RING;
-        if ((2 * N) % L) return TFT_E_RING;
-        if (N < bits) return TFT_E_RANGE;
-    } else {
-        uint64_t W = 1;
-        while (32 * W < bits || 64 * W < L) W <<= 1;
-        if (W > 4096) return TFT_E_UNSUPPORTED;
-        N = 32 * W;
-    }
-    o->N = (uint32_t)N;
-    o->W = (uint32_t)(N / 32);
-    o->l = l;
-    o->n = n;
-    o->L = L;
-    o->ws = 2 * L * (o->W + 1) * 4ull;
-    return TFT_OK;
-}
-
 int zx_mul_ss_workspace(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h_limbs,
                         const tft_ss_params *params, uint64_t *bytes) {
     if (!bytes) return TFT_E_ARG;
     SSShape sh;
     int st = ss_shape(len_g, g_limbs, len_h, h_limbs, params, &sh);
     if (st) return st;
-    *bytes = sh.ws;
+    *bytes = sh.bytes;
     return TFT_OK;
 }
 
@@ -435,15 +402,14 @@ static int ss_run(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uin
     SSShape sh;
     int st = ss_shape(len_g, g_limbs, len_h, h_limbs, params, &sh);
     if (st) return st;
-    const uint64_t bits = 32ull * (g_limbs + h_limbs) + log2u(std::min(len_g, len_h));
-    if (32ull * out_limbs < bits) return TFT_E_RANGE;
-    if (!ws || ws_bytes < sh.ws) return TFT_E_WORKSPACE;
+    if (32ull * out_limbs < sh.bits) return TFT_E_RANGE;
+    if (!ws || ws_bytes < sh.bytes) return TFT_E_WORKSPACE;
     tft_ring ring{TFT_RING_FERMAT, sh.N, 0, 0, 0};
     uint32_t *A = static_cast<uint32_t *>(ws);
     uint32_t *B = A + sh.L * (sh.W + 1);
     const tft_split *split = params ? &params->split : nullptr;
-    tft_plan *pg = cached_plan(&ring, 0, sh.l, 0, len_g, sh.n, 0, split);
-    tft_plan *ph = cached_plan(&ring, 0, sh.l, 0, len_h, sh.n, 0, split);
+    tft_plan *pg = cached_plan(&ring, 0, sh.l, 0, sh.zg, sh.n, 0, split);
+    tft_plan *ph = cached_plan(&ring, 0, sh.l, 0, sh.zh, sh.n, 0, split);
     tft_plan *pi = cached_plan(&ring, 1, sh.l, 0, sh.n, sh.n, 0, split);
     hipEvent_t ev[7] = {};
     LaunchTimer lt;
@@ -456,8 +422,10 @@ static int ss_run(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uin
     }
     auto mark = [&](int i) { return tm ? hipEventRecord(ev[i], hs) : hipSuccess; };
     hipError_t e = mark(0);
-    if (e == hipSuccess) e = launch_fermat_pack(sh.W, g, len_g, g_limbs, A, sh.L, hs);
-    if (e == hipSuccess) e = launch_fermat_pack(sh.W, h, len_h, h_limbs, B, sh.L, hs);
+    const PackDesc dg{g, len_g, 0, sh.zg, g_limbs, sh.k, sh.ws, 0};
+    const PackDesc dh{h, len_h, 0, sh.zh, h_limbs, sh.k, sh.ws, 0};
+    if (e == hipSuccess) e = launch_fermat_pack(sh.W, nullptr, 1, dg, sh.zg, A, sh.L, hs);
+    if (e == hipSuccess) e = launch_fermat_pack(sh.W, nullptr, 1, dh, sh.zh, B, sh.L, hs);
     if (e == hipSuccess) e = mark(1);
     if (e != hipSuccess) st = dev_fail(e, "pack");
     if (!st) st = plan_run(pg, A, hs, ltp);
@@ -472,7 +440,8 @@ static int ss_run(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uin
     if (!st) st = plan_run(pi, A, hs, ltp);
     if (!st && (e = mark(5)) != hipSuccess) st = dev_fail(e, "event");
     if (!st) {
-        e = launch_fermat_unpack(sh.W, A, sh.L, sh.n, out, out_limbs, hs);
+        const UnpackDesc du{out, len_g + len_h - 1, 0, sh.n, out_limbs, sh.k, sh.ws, 0};
+        e = launch_fermat_unpack(sh.W, nullptr, 1, du, len_g + len_h - 1, out_limbs, sh.k > 1, A, sh.L, hs);
         if (e == hipSuccess) e = mark(6);
         if (e != hipSuccess) st = dev_fail(e, "unpack");
     }

@@ -57,6 +57,31 @@ struct Job {
 
 static_assert(sizeof(Job) == 32, "Job layout");
 
+// One operand of a Schoenhage-Strassen product: len coefficients of climbs
+// limbs, k per cell in slots of ws limbs, written to cells [cell0, cell0 + z).
+struct PackDesc {
+    const uint32_t *coef;
+    uint64_t len;
+    uint64_t cell0;
+    uint64_t z;
+    uint32_t climbs;
+    uint32_t k;
+    uint32_t ws;
+    uint32_t pad;
+};
+
+// One product: len_out coefficients of olimbs limbs from the ncells cells at cell0.
+struct UnpackDesc {
+    uint32_t *out;
+    uint64_t len_out;
+    uint64_t cell0;
+    uint64_t ncells;
+    uint32_t olimbs;
+    uint32_t k;
+    uint32_t ws;
+    uint32_t pad;
+};
+
 inline uint32_t op_code(const LeafOp &o) { return o.w0 & 15u; }
 inline uint32_t op_i0(const LeafOp &o) { return (o.w0 >> 4) & 16383u; }
 inline uint32_t op_i1(const LeafOp &o) { return (o.w0 >> 18) & 16383u; }

@@ -166,10 +166,11 @@ constexpr uint32_t pw_threads(int W) {
     return (t + 63) / 64 * 64;
 }
 
+// c = a b 2^scale_e for one product; a, b, c are W-limb cells (c may alias a or b),
+// ta, tb their top words, tc where c's top goes.  Called by a whole workgroup.
 template <int S, int C>
-__global__ void __launch_bounds__(256) fermat_pointwise_kernel(const uint32_t *__restrict__ a,
-                                                               const uint32_t *__restrict__ b, uint32_t *c,
-                                                               uint64_t cap, uint32_t scale_e) {
+__device__ __forceinline__ void pointwise_body(const uint32_t *a, uint32_t ta, const uint32_t *b, uint32_t tb,
+                                               uint32_t *c, uint32_t *tc, uint32_t scale_e) {
     using F = FChunk<S, C>;
     constexpr int W = F::W;
     extern __shared__ uint32_t sm[];
@@ -177,14 +178,12 @@ __global__ void __launch_bounds__(256) fermat_pointwise_kernel(const uint32_t *_
     uint32_t *P0 = Bv + W, *P1 = P0 + W, *P2 = P1 + W, *N0 = P2 + W, *N1 = N0 + W, *N2 = N1 + W;
     uint32_t *Y = N2 + W;  // F::ESZ dwords, LDS layout of one element
     uint32_t &topY = Y[F::ESZ];
-    const uint64_t i = blockIdx.x;
     const uint32_t tid = threadIdx.x, nthr = blockDim.x;
 
     for (uint32_t q = tid; q < (uint32_t)W; q += nthr) {
-        A[q] = a[i * W + q];
-        Bv[q] = b[i * W + q];
+        A[q] = a[q];
+        Bv[q] = b[q];
     }
-    const uint32_t ta = a[cap * W + i], tb = b[cap * W + i];
     __syncthreads();
 
     const bool special = (ta | tb) != 0u;
@@ -312,30 +311,86 @@ __global__ void __launch_bounds__(256) fermat_pointwise_kernel(const uint32_t *_
         }
     }
     __syncthreads();
-    for (uint32_t q = tid; q < (uint32_t)W; q += nthr) c[i * W + q] = Y[F::addr(q)];
-    if (tid == 0) c[cap * W + i] = topY;
+    for (uint32_t q = tid; q < (uint32_t)W; q += nthr) c[q] = Y[F::addr(q)];
+    if (tid == 0) *tc = topY;
 }
 
-__global__ void fermat_pack_kernel(const uint32_t *__restrict__ coef, uint64_t count, uint32_t climbs,
-                                   uint32_t *__restrict__ x, uint64_t cap, uint32_t W) {
-    const uint64_t total = count * (uint64_t)W;
+template <int S, int C>
+__global__ void __launch_bounds__(256) fermat_pointwise_kernel(const uint32_t *__restrict__ a,
+                                                               const uint32_t *__restrict__ b, uint32_t *c,
+                                                               uint64_t cap, uint32_t scale_e) {
+    constexpr int W = S * C;
+    const uint64_t i = blockIdx.x;
+    pointwise_body<S, C>(a + i * W, a[cap * W + i], b + i * W, b[cap * W + i], c + i * W, c + cap * W + i, scale_e);
+}
+
+// Pointwise products over a list: item i multiplies cells it.x and it.y of the
+// cell array x (capacity cap) into cell it.x, with its own scale 2^it.z.
+template <int S, int C>
+__global__ void __launch_bounds__(256) fermat_pointwise_items_kernel(uint32_t *x, uint64_t cap,
+                                                                     const uint4 *__restrict__ items) {
+    constexpr int W = S * C;
+    const uint4 it = items[blockIdx.x];
+    uint32_t *ca = x + (uint64_t)it.x * W, *cb = x + (uint64_t)it.y * W;
+    pointwise_body<S, C>(ca, x[cap * W + it.x], cb, x[cap * W + it.y], ca, x + cap * W + it.x, it.z);
+}
+
+// Pack: cell e of an operand holds coefficients e*k .. e*k+k-1, coefficient
+// e*k+j in limbs [j*ws, j*ws + climbs) (slot j), zeros elsewhere (Sect. 5.1 with
+// k = 1; k > 1 bundles k coefficients per ring element).  One descriptor per
+// operand, blockIdx.y selects it.
+__global__ void fermat_pack_kernel(const PackDesc *__restrict__ descs, PackDesc inl, uint32_t *__restrict__ x,
+                                   uint64_t cap, uint32_t W) {
+    const PackDesc d = descs ? descs[blockIdx.y] : inl;
+    const uint64_t total = d.z * (uint64_t)W;
     for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < total;
          q += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t cell = q / W;
-        const uint32_t t = (uint32_t)(q % W);
-        x[q] = t < climbs ? coef[cell * climbs + t] : 0u;
-        if (t == 0) x[cap * W + cell] = 0u;
+        const uint64_t e = q / W;
+        const uint32_t p = (uint32_t)(q % W);
+        const uint32_t j = p / d.ws, off = p % d.ws;
+        const uint64_t c = e * d.k + j;
+        x[(d.cell0 + e) * W + p] = (j < d.k && off < d.climbs && c < d.len) ? d.coef[c * d.climbs + off] : 0u;
+        if (p == 0) x[cap * W + d.cell0 + e] = 0u;
     }
 }
 
-__global__ void fermat_unpack_kernel(const uint32_t *__restrict__ x, uint64_t cap, uint64_t count,
-                                     uint32_t *__restrict__ out, uint32_t olimbs, uint32_t W) {
-    const uint64_t total = count * (uint64_t)olimbs;
+// Unpack with k = 1: coefficient t is the low limbs of cell t.
+__global__ void fermat_unpack1_kernel(const UnpackDesc *__restrict__ descs, UnpackDesc inl,
+                                      const uint32_t *__restrict__ x, uint64_t cap, uint32_t W) {
+    const UnpackDesc d = descs ? descs[blockIdx.y] : inl;
+    const uint64_t total = d.len_out * (uint64_t)d.olimbs;
     for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < total;
          q += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t cell = q / olimbs;
-        const uint32_t t = (uint32_t)(q % olimbs);
-        out[q] = t < W ? x[cell * W + t] : (t == W ? x[cap * W + cell] : 0u);
+        const uint64_t t = q / d.olimbs;
+        const uint32_t i = (uint32_t)(q % d.olimbs);
+        const uint64_t cell = d.cell0 + t;
+        d.out[q] = i < W ? x[cell * W + i] : (i == W ? x[cap * W + cell] : 0u);
+    }
+}
+
+// Unpack with k > 1: the product cell m holds slots 0..2k-2 of width ws limbs;
+// coefficient t = m k + j is slot j of cell m plus slot j + k of cell m - 1.
+__global__ void fermat_unpackk_kernel(const UnpackDesc *__restrict__ descs, UnpackDesc inl,
+                                      const uint32_t *__restrict__ x, uint32_t W) {
+    const UnpackDesc d = descs ? descs[blockIdx.y] : inl;
+    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < d.len_out;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t m = t / d.k;
+        const uint32_t j = (uint32_t)(t % d.k);
+        const uint32_t *s0 = (m < d.ncells) ? x + (d.cell0 + m) * W + (uint64_t)j * d.ws : nullptr;
+        const uint32_t *s1 = (m >= 1 && j + 1 < d.k && m - 1 < d.ncells)
+                                 ? x + (d.cell0 + m - 1) * W + (uint64_t)(j + d.k) * d.ws
+                                 : nullptr;
+        uint32_t *o = d.out + t * d.olimbs;
+        uint64_t c = 0;
+        for (uint32_t i = 0; i < d.olimbs; ++i) {
+            if (i < d.ws) {
+                c += (s0 ? s0[i] : 0u);
+                c += (s1 ? s1[i] : 0u);
+            }
+            o[i] = (uint32_t)c;
+            c >>= 32;
+        }
     }
 }
 
@@ -358,6 +413,15 @@ hipError_t leaf_launch(uint32_t nwaves, uint32_t njobs, uint32_t lds_cells, cons
     return hipGetLastError();
 }
 
+template <class KernelT>
+hipError_t pointwise_attr(KernelT *kern, size_t lds, bool &done) {
+    if (done || lds <= 65536) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
+    if (e == hipSuccess) done = true;
+    return e;
+}
+
 template <int S, int C>
 hipError_t pointwise_launch(uint64_t n, const uint32_t *a, const uint32_t *b, uint32_t *c, uint64_t cap,
                             uint32_t scale_e, hipStream_t st) {
@@ -365,15 +429,23 @@ hipError_t pointwise_launch(uint64_t n, const uint32_t *a, const uint32_t *b, ui
     const size_t lds = (size_t)(8 * W + FChunk<S, C>::ESZ + 1) * 4;
     if (lds > kLdsBudget) return hipErrorInvalidValue;
     static bool attr = false;
-    if (!attr && lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fermat_pointwise_kernel<S, C>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    const uint32_t thr = pw_threads(W);
-    hipLaunchKernelGGL((fermat_pointwise_kernel<S, C>), dim3((uint32_t)n), dim3(thr), lds, st, a, b, c, cap,
-                       scale_e);
+    hipError_t e = pointwise_attr(&fermat_pointwise_kernel<S, C>, lds, attr);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((fermat_pointwise_kernel<S, C>), dim3((uint32_t)n), dim3(pw_threads(W)), lds, st, a, b, c,
+                       cap, scale_e);
+    return hipGetLastError();
+}
+
+template <int S, int C>
+hipError_t pointwise_items_launch(uint64_t nitems, uint32_t *x, uint64_t cap, const uint4 *items, hipStream_t st) {
+    constexpr int W = S * C;
+    const size_t lds = (size_t)(8 * W + FChunk<S, C>::ESZ + 1) * 4;
+    if (lds > kLdsBudget) return hipErrorInvalidValue;
+    static bool attr = false;
+    hipError_t e = pointwise_attr(&fermat_pointwise_items_kernel<S, C>, lds, attr);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((fermat_pointwise_items_kernel<S, C>), dim3((uint32_t)nitems), dim3(pw_threads(W)), lds, st,
+                       x, cap, items);
     return hipGetLastError();
 }
 
@@ -419,23 +491,35 @@ hipError_t launch_fermat_pointwise(uint32_t W, uint64_t n, const uint32_t *a, co
     TFT_FERMAT_DISPATCH(W, pointwise_launch, n, a, b, c, cap, scale_e, st)
 }
 
-hipError_t launch_fermat_pack(uint32_t W, const uint32_t *coef, uint64_t count, uint32_t climbs, uint32_t *x,
-                              uint64_t cap, hipStream_t st) {
-    if (count == 0) return hipSuccess;
-    const uint64_t total = count * W;
-    uint32_t blocks = (uint32_t)((total + 255) / 256);
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(fermat_pack_kernel, dim3(blocks), dim3(256), 0, st, coef, count, climbs, x, cap, W);
+hipError_t launch_fermat_pointwise_items(uint32_t W, uint64_t nitems, uint32_t *x, uint64_t cap, const uint4 *items,
+                                         hipStream_t st) {
+    if (nitems == 0) return hipSuccess;
+    TFT_FERMAT_DISPATCH(W, pointwise_items_launch, nitems, x, cap, items, st)
+}
+
+hipError_t launch_fermat_pack(uint32_t W, const PackDesc *descs, uint32_t ndesc, const PackDesc &inl, uint64_t max_z,
+                              uint32_t *x, uint64_t cap, hipStream_t st) {
+    if (ndesc == 0 || max_z == 0) return hipSuccess;
+    uint64_t blocks = (max_z * W + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fermat_pack_kernel, dim3((uint32_t)blocks, ndesc), dim3(256), 0, st, descs, inl, x, cap, W);
     return hipGetLastError();
 }
 
-hipError_t launch_fermat_unpack(uint32_t W, const uint32_t *x, uint64_t cap, uint64_t count, uint32_t *out,
-                                uint32_t olimbs, hipStream_t st) {
-    if (count == 0) return hipSuccess;
-    const uint64_t total = count * olimbs;
-    uint32_t blocks = (uint32_t)((total + 255) / 256);
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(fermat_unpack_kernel, dim3(blocks), dim3(256), 0, st, x, cap, count, out, olimbs, W);
+hipError_t launch_fermat_unpack(uint32_t W, const UnpackDesc *descs, uint32_t ndesc, const UnpackDesc &inl,
+                                uint64_t max_len, uint32_t max_olimbs, bool bundled, const uint32_t *x, uint64_t cap,
+                                hipStream_t st) {
+    if (ndesc == 0 || max_len == 0) return hipSuccess;
+    if (!bundled) {
+        uint64_t blocks = (max_len * max_olimbs + 255) / 256;
+        if (blocks > 4096) blocks = 4096;
+        hipLaunchKernelGGL(fermat_unpack1_kernel, dim3((uint32_t)blocks, ndesc), dim3(256), 0, st, descs, inl, x, cap,
+                           W);
+    } else {
+        uint64_t blocks = (max_len + 255) / 256;
+        if (blocks > 4096) blocks = 4096;
+        hipLaunchKernelGGL(fermat_unpackk_kernel, dim3((uint32_t)blocks, ndesc), dim3(256), 0, st, descs, inl, x, W);
+    }
     return hipGetLastError();
 }
 

@@ -16,13 +16,20 @@ hipError_t launch_fermat_leaf(uint32_t W, uint32_t nwaves, uint32_t njobs, uint3
 hipError_t launch_fermat_pointwise(uint32_t W, uint64_t n, const uint32_t *a, const uint32_t *b, uint32_t *c,
                                    uint64_t cap, uint32_t scale_e, hipStream_t st);
 
-// Coefficients (climbs limbs each) -> cells [0, count) of a cell array of capacity cap.
-hipError_t launch_fermat_pack(uint32_t W, const uint32_t *coef, uint64_t count, uint32_t climbs, uint32_t *x,
-                              uint64_t cap, hipStream_t st);
+// Pointwise products over an item list on one cell array (see fermat_pointwise_items_kernel).
+hipError_t launch_fermat_pointwise_items(uint32_t W, uint64_t nitems, uint32_t *x, uint64_t cap, const uint4 *items,
+                                         hipStream_t st);
 
-// Cells [0, count) -> coefficients of olimbs limbs (low limbs of the canonical residue).
-hipError_t launch_fermat_unpack(uint32_t W, const uint32_t *x, uint64_t cap, uint64_t count, uint32_t *out,
-                                uint32_t olimbs, hipStream_t st);
+// Coefficients -> cells, one descriptor per operand: a device array of ndesc
+// descriptors, or (descs == nullptr, ndesc == 1) the descriptor inl passed by value.
+hipError_t launch_fermat_pack(uint32_t W, const PackDesc *descs, uint32_t ndesc, const PackDesc &inl, uint64_t max_z,
+                              uint32_t *x, uint64_t cap, hipStream_t st);
+
+// Cells -> coefficients, one descriptor per product (device array or inl as above);
+// bundled = the descriptors have k > 1 (all of one launch alike).
+hipError_t launch_fermat_unpack(uint32_t W, const UnpackDesc *descs, uint32_t ndesc, const UnpackDesc &inl,
+                                uint64_t max_len, uint32_t max_olimbs, bool bundled, const uint32_t *x, uint64_t cap,
+                                hipStream_t st);
 
 // Largest LDS bytes one workgroup may use.
 uint32_t lds_budget_bytes();

@@ -1,0 +1,64 @@
+// Shape of a Schoenhage-Strassen product in Z[x] over R = Z/(2^N+1) (Sect. 5.1),
+// with k >= 1 coefficients bundled per ring element: the operands become
+// polynomials in X = x^k whose coefficients are k-slot integers (slot width ws
+// limbs, wide enough for any output coefficient); a product cell then holds
+// 2k-1 slots, so N >= 32 (2k-1) ws, and L = 2^l must divide 2N.
+#pragma once
+#include <stdint.h>
+
+#include "../../include/tft.h"
+
+namespace tft {
+
+struct SSShape {
+    uint32_t N, W, l, k, ws;
+    uint64_t zg, zh, n, L, bytes;
+    uint64_t bits;  // bound on the bits of an output coefficient
+};
+
+inline uint32_t ss_log2u(uint64_t v) {
+    uint32_t l = 0;
+    while ((1ull << l) < v) l++;
+    return l;
+}
+
+inline int ss_shape(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h_limbs, const tft_ss_params *p,
+                    SSShape *o) {
+    if (len_g < 1 || len_h < 1 || g_limbs < 1 || h_limbs < 1) return TFT_E_ARG;
+    const uint32_t k = (p && p->k) ? p->k : 1u;
+    if (k > 64) return TFT_E_ARG;
+    const uint64_t bits = 32ull * (g_limbs + h_limbs) + ss_log2u(len_g < len_h ? len_g : len_h);
+    const uint64_t ws = (bits + 31) / 32;
+    const uint64_t zg = (len_g + k - 1) / k, zh = (len_h + k - 1) / k;
+    const uint64_t n = zg + zh - 1;
+    const uint32_t l = (p && p->l) ? p->l : (ss_log2u(n) < 1 ? 1u : ss_log2u(n));
+    if (l > 24 || (1ull << l) < n) return TFT_E_ARG;
+    const uint64_t L = 1ull << l;
+    const uint64_t need = (k == 1) ? ws : (2ull * k - 1) * ws;  // limbs a product cell needs
+    uint64_t W;
+    if (p && p->N) {
+        if (p->N % 32) return TFT_E_RING;
+        W = p->N / 32;
+        if ((W & (W - 1)) || W > 4096) return TFT_E_RING;
+        if ((64 * W) % L) return TFT_E_RING;
+        if (W < need) return TFT_E_RANGE;
+    } else {
+        W = 1;
+        while (W < need || 64 * W < L) W <<= 1;
+        if (W > 4096) return TFT_E_UNSUPPORTED;
+    }
+    o->N = (uint32_t)(32 * W);
+    o->W = (uint32_t)W;
+    o->l = l;
+    o->k = k;
+    o->ws = (uint32_t)ws;
+    o->zg = zg;
+    o->zh = zh;
+    o->n = n;
+    o->L = L;
+    o->bytes = 2 * L * (W + 1) * 4ull;
+    o->bits = bits;
+    return TFT_OK;
+}
+
+}  // namespace tft

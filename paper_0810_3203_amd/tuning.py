@@ -1,0 +1,73 @@
+"""Host orchestration of parameter selection for batches of Z[x] products.
+
+Gathers exhaustive timings (tft_ss_time) of every candidate of a set of
+requests, turns them into training rows for the cost model (features from
+tft_ss_features, target = log of the median time in ms), and applies the
+three selection policies: the fixed default rule, the exhaustive best per
+request, and the cost model's argmin.  The timing, training and inference all
+run in libtft.so; this module only loops and marshals.
+"""
+
+import math
+
+from . import _binding as B
+
+
+def _ws_for(cands, req, torch, device):
+    need = max(B.zx_mul_ss_workspace(req.len_g, req.g_limbs, req.len_h, req.h_limbs, c) for c in cands)
+    return torch.empty(need, dtype=torch.uint8, device=device)
+
+
+def time_candidates(reqs, reps=3, device="cuda", stream=None):
+    """For each ZXRequest: (candidates, median ms per candidate, index of the fastest)."""
+    import torch
+    out = []
+    for r in reqs:
+        cands = B.ss_candidates(r.len_g, r.g_limbs, r.len_h, r.h_limbs)
+        ws = _ws_for(cands, r, torch, device)
+        ms, best = B.ss_time(r, cands, reps, ws, stream)
+        out.append((cands, ms, best))
+        del ws
+    return out
+
+
+def training_rows(reqs, timings):
+    """Features (rows x SS_FEATURES) and targets log(ms) from time_candidates output."""
+    X, y = [], []
+    for r, (cands, ms, _) in zip(reqs, timings):
+        for c, t in zip(cands, ms):
+            X.append(B.ss_features(r.len_g, r.g_limbs, r.len_h, r.h_limbs, c))
+            y.append(math.log(max(t, 1e-4)))
+    return X, y
+
+
+def train_model(X, y, hidden=64, depth=3, iters=3000, lr=2e-3, seed=11, device="cuda"):
+    """A new MLP trained full-batch with Adam; returns (model, final loss)."""
+    import torch
+    m = B.MLP(B.SS_FEATURES, hidden, depth, seed)
+    xt = torch.tensor(X, dtype=torch.float32, device=device).contiguous()
+    yt = torch.tensor(y, dtype=torch.float32, device=device).contiguous()
+    loss = m.train(xt, yt, iters, lr)
+    return m, loss
+
+
+def same_params(a, b):
+    return (a.k or 1) == (b.k or 1) and a.N == b.N and a.l == b.l and a.split.top_l1 == b.split.top_l1 \
+        and a.split.leaf_log2 == b.split.leaf_log2
+
+
+def policy_times(reqs, timings, model=None):
+    """Per request: time of the default rule's candidate, of the model's choice
+    (if a model is given) and of the exhaustive best, all from the timing table."""
+    rows = []
+    arr = B.requests_array(reqs)
+    if model is not None:
+        model.choose(arr)
+    for i, (r, (cands, ms, best)) in enumerate(zip(reqs, timings)):
+        d = B.ss_default_params(r.len_g, r.g_limbs, r.len_h, r.h_limbs)
+        t_def = next(t for c, t in zip(cands, ms) if same_params(c, d))
+        t_mlp = None
+        if model is not None:
+            t_mlp = next(t for c, t in zip(cands, ms) if same_params(c, arr[i].params))
+        rows.append(dict(default=t_def, mlp=t_mlp, best=ms[best], k1=ms[0]))
+    return rows

@@ -1,0 +1,135 @@
+"""GPU checks of the cost model and the parameter selection.
+
+- MLP forward, gradient and Adam step (HIP kernels) against the fp64 oracle
+  (oracle/mlp_oracle.py, itself pinned by finite differences);
+- training lowers the loss;
+- exhaustive timing picks the first minimum; the model's choices are valid
+  candidates; regret of the model against the exhaustive best and its gain
+  over the default rule on held-out requests of the batch workload.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as MO
+from synth import workloads as wl
+from tests.gpu_util import note, u32_to_device
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_0810_3203_amd as T  # noqa: E402
+from paper_0810_3203_amd import tuning  # noqa: E402
+
+DIMS = MO.layer_dims(T.SS_FEATURES, 64, 3)
+
+
+def _model_and_data(seed=5, rows=37):
+    m = T.MLP(T.SS_FEATURES, 64, 3, seed)
+    assert m.param_count == MO.param_count(T.SS_FEATURES, 64, 3)
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0, 1, (rows, T.SS_FEATURES)).astype(np.float32)
+    t = rng.normal(0, 1, rows).astype(np.float32)
+    return m, x, t
+
+
+def test_forward_matches_oracle():
+    m, x, _ = _model_and_data()
+    p = np.array(m.get_params(), dtype=np.float64)
+    y = torch.empty(x.shape[0], dtype=torch.float32, device="cuda")
+    note("mlp forward")
+    m.forward(torch.from_numpy(x).cuda(), y)
+    ref, _, _ = MO.forward(p, DIMS, x.astype(np.float64))
+    got = y.cpu().numpy().astype(np.float64)
+    assert np.allclose(got, ref, rtol=1e-4, atol=1e-4 * np.abs(ref).max())
+
+
+def test_gradient_matches_oracle():
+    m, x, t = _model_and_data(seed=9, rows=53)
+    p = np.array(m.get_params(), dtype=np.float64)
+    grad = torch.empty(m.param_count, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    note("mlp gradient")
+    m.gradient(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(), grad, loss)
+    ref = MO.gradient(p, DIMS, x.astype(np.float64), t.astype(np.float64))
+    got = grad.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
+    assert np.allclose(got, ref, rtol=1e-3, atol=1e-4 * np.abs(ref).max())
+    assert float(loss.item()) == pytest.approx(MO.loss(p, DIMS, x.astype(np.float64), t.astype(np.float64)),
+                                               rel=1e-4)
+
+
+def test_adam_step_matches_oracle():
+    m, x, t = _model_and_data(seed=13, rows=29)
+    p0 = np.array(m.get_params(), dtype=np.float64)
+    lr = 1e-3
+    note("mlp one Adam step")
+    m.train(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(), 1, lr)
+    p1 = np.array(m.get_params(), dtype=np.float64)
+    g = MO.gradient(p0, DIMS, x.astype(np.float64), t.astype(np.float64))
+    ref, _, _ = MO.adam(p0, g, np.zeros_like(p0), np.zeros_like(p0), 1, lr)
+    clear = np.abs(g) > 1e-3 * np.abs(g).max()  # the step's direction is well defined there
+    assert clear.sum() > 0.3 * g.size
+    assert np.allclose(p1[clear], ref[clear], rtol=0, atol=1e-6)
+    assert np.all(np.abs(p1 - p0) <= lr * 1.0001 + 1e-7)
+
+
+def test_training_lowers_loss():
+    rng = np.random.default_rng(21)
+    x = rng.uniform(0, 1, (200, T.SS_FEATURES)).astype(np.float32)
+    t = (np.sin(3 * x[:, 0]) + x[:, 1] * x[:, 2] - 0.5 * x[:, 3]).astype(np.float32)
+    m = T.MLP(T.SS_FEATURES, 64, 3, 3)
+    xt, tt = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    p = np.array(m.get_params(), dtype=np.float64)
+    l0 = MO.loss(p, DIMS, x.astype(np.float64), t.astype(np.float64))
+    note("mlp training")
+    l1 = m.train(xt, tt, 1500, 3e-3)
+    assert l1 < 0.05 * l0
+
+
+def _requests(indices, scale=1):
+    """Requests of the batch workload (lengths divided by `scale`), with device tensors."""
+    keep, reqs = [], []
+    for i in indices:
+        g, h = wl.batch_request(i, len_lo=max(1, 100 // scale), len_hi=20000 // scale)
+        ow = (32 * (g.shape[1] + h.shape[1]) + (min(g.shape[0], h.shape[0]) - 1).bit_length() + 31) // 32
+        dg, dh = u32_to_device(g, torch), u32_to_device(h, torch)
+        out = torch.zeros((g.shape[0] + h.shape[0] - 1, ow), dtype=torch.int32, device="cuda")
+        keep.append((dg, dh, out))
+        reqs.append(T.zx_request(dg, dh, out))
+    return keep, reqs
+
+
+def test_exhaustive_timing_first_minimum():
+    keep, reqs = _requests([3], scale=4)
+    note("tft_ss_time on one request")
+    (cands, ms, best), = tuning.time_candidates(reqs, reps=3)
+    assert len(ms) == len(cands) and all(v > 0 for v in ms)
+    assert best == int(np.argmin(np.array(ms)))
+
+
+def test_model_regret_and_gain():
+    keep_tr, train = _requests(range(1000, 1032), scale=2)
+    keep_te, test = _requests(range(2000, 2012), scale=2)
+    note("timing %d training requests" % len(train))
+    tr = tuning.time_candidates(train, reps=3)
+    X, y = tuning.training_rows(train, tr)
+    note("training on %d rows" % len(X))
+    model, loss = tuning.train_model(X, y, iters=3000)
+    assert math.isfinite(loss) and loss < 0.05
+    note("timing %d held-out requests" % len(test))
+    te = tuning.time_candidates(test, reps=3)
+    rows = tuning.policy_times(test, te, model)
+    t_best = sum(r["best"] for r in rows)
+    t_mlp = sum(r["mlp"] for r in rows)
+    t_def = sum(r["default"] for r in rows)
+    regret = t_mlp / t_best - 1
+    print("held-out: best %.2f ms, model %.2f ms (regret %.3f), default %.2f ms, k=1 %.2f ms"
+          % (t_best, t_mlp, regret, t_def, sum(r["k1"] for r in rows)), flush=True)
+    assert regret < 0.25
+    assert t_mlp <= 1.05 * t_def
