@@ -91,12 +91,149 @@ def cpu_baseline(g_limbs_arr, N, l, z, n, alg_bytes, budget_s=15.0):
                                                                                           total_s)}
 
 
+def _progress(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def batch_leg(T, torch, count=4096, train_count=32, heldout=16, replays=3, k1_stride=16):
+    """Many Z[x] products of uneven lengths: batched plan (cost-model parameters,
+    hipGraph replay) against one-at-a-time zx_mul_ss with the default rule;
+    outputs compared bit for bit on the device."""
+    from paper_0810_3203_amd import tuning
+    from synth import device as dev
+
+    t0 = time.perf_counter()
+    ops = [dev.batch_request(torch, i, "cuda") for i in range(count)]
+    outs_b, outs_s, reqs = [], [], []
+    for g, h in ops:
+        ow = (32 * (g.shape[1] + h.shape[1]) + (min(g.shape[0], h.shape[0]) - 1).bit_length() + 31) // 32
+        ob = torch.empty((g.shape[0] + h.shape[0] - 1, ow), dtype=torch.int32, device="cuda")
+        outs_b.append(ob)
+        outs_s.append(torch.empty_like(ob))
+        reqs.append(T.zx_request(g, h, ob))
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    _progress("batch: %d requests generated in %.1f s" % (count, gen_s))
+
+    # cost model: exhaustive timings of requests outside the batch, then training
+    t0 = time.perf_counter()
+    extra = [dev.batch_request(torch, 100000 + i, "cuda") for i in range(train_count + heldout)]
+    ereq, keep = [], []
+    for g, h in extra:
+        ow = (32 * (g.shape[1] + h.shape[1]) + (min(g.shape[0], h.shape[0]) - 1).bit_length() + 31) // 32
+        o = torch.empty((g.shape[0] + h.shape[0] - 1, ow), dtype=torch.int32, device="cuda")
+        keep.append(o)
+        ereq.append(T.zx_request(g, h, o))
+    tim = tuning.time_candidates(ereq[:train_count], reps=3)
+    X, y = tuning.training_rows(ereq[:train_count], tim)
+    tune_s = time.perf_counter() - t0
+    _progress("batch: %d training requests timed in %.1f s" % (train_count, tune_s))
+    t0 = time.perf_counter()
+    model, loss = tuning.train_model(X, y, iters=3000)
+    train_s = time.perf_counter() - t0
+    ho = tuning.time_candidates(ereq[train_count:], reps=3)
+    rows = tuning.policy_times(ereq[train_count:], ho, model)
+    t_best = sum(r["best"] for r in rows)
+    t_mlp = sum(r["mlp"] for r in rows)
+    t_def = sum(r["default"] for r in rows)
+    del keep, extra, ereq
+    _progress("batch: model trained (loss %.4f), held-out regret %.3f" % (loss, t_mlp / t_best - 1))
+
+    arr = T.requests_array(reqs)
+    t0 = time.perf_counter()
+    model.choose(arr)
+    choose_s = time.perf_counter() - t0
+    ks = {}
+    for r in arr:
+        ks[r.params.k] = ks.get(r.params.k, 0) + 1
+
+    t0 = time.perf_counter()
+    plan = T.BatchPlan(arr, max_workspace=96 << 30)
+    plan_s = time.perf_counter() - t0
+    assert all(s == 0 for s in plan.status())
+    ws = torch.empty(plan.workspace, dtype=torch.uint8, device="cuda")
+    plan.execute(ws, use_graph=True)  # direct run + capture
+    plan.execute(ws, use_graph=True)  # first replay
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(replays):
+        plan.execute(ws, use_graph=True)
+    e1.record()
+    torch.cuda.synchronize()
+    batch_ms = e0.elapsed_time(e1) / replays
+    _progress("batch: graph replay %.1f ms (%d launches)" % (batch_ms, plan.launches))
+    launches = plan.launches
+    plan.close()
+    del ws
+
+    # one at a time, default rule, no graph
+    params = [T.ss_default_params(g.shape[0], g.shape[1], h.shape[0], h.shape[1]) for g, h in ops]
+    need = max(T.zx_mul_ss_workspace(g.shape[0], g.shape[1], h.shape[0], h.shape[1], p)
+               for (g, h), p in zip(ops, params))
+    ws1 = torch.empty(need, dtype=torch.uint8, device="cuda")
+
+    def one_pass(sel, par, outs):
+        for i in sel:
+            g, h = ops[i]
+            T.zx_mul_ss(g, h, outs[i], par[i], ws=ws1)
+
+    one_pass(range(count), params, outs_s)  # builds and uploads every shape's plans
+    torch.cuda.synchronize()
+    e0.record()
+    one_pass(range(count), params, outs_s)
+    e1.record()
+    torch.cuda.synchronize()
+    single_ms = e0.elapsed_time(e1)
+    _progress("batch: one at a time %.1f ms" % single_ms)
+    exact = all(torch.equal(a, b) for a, b in zip(outs_b, outs_s))
+
+    # the paper's literal product (k = 1) one at a time, on every k1_stride-th request
+    p1 = [T.SSParams(0, 0, T.Split(0, 0), 1)] * count
+    sel = list(range(0, count, k1_stride))
+    need1 = max(T.zx_mul_ss_workspace(ops[i][0].shape[0], ops[i][0].shape[1], ops[i][1].shape[0],
+                                      ops[i][1].shape[1], p1[i]) for i in sel)
+    del ws1
+    ws1 = torch.empty(need1, dtype=torch.uint8, device="cuda")
+    one_pass(sel, p1, outs_s)
+    torch.cuda.synchronize()
+    e0.record()
+    one_pass(sel, p1, outs_s)
+    e1.record()
+    torch.cuda.synchronize()
+    k1_ms = e0.elapsed_time(e1) * count / len(sel)
+    exact_k1 = all(torch.equal(outs_b[i], outs_s[i]) for i in sel)
+    del ws1
+
+    muls = count / (batch_ms * 1e-3)
+    return {
+        "workload": "%d Z[x] products, lengths uniform in [100, 20000], 1000-bit coefficients" % count,
+        "muls_per_s": round(muls, 1),
+        "batch_ms": round(batch_ms, 3),
+        "launches": launches,
+        "one_at_a_time_muls_per_s": round(count / (single_ms * 1e-3), 1),
+        "one_at_a_time_ms": round(single_ms, 3),
+        "speedup_vs_one_at_a_time": round(single_ms / batch_ms, 3),
+        "k1_one_at_a_time_ms_extrapolated": round(k1_ms, 3),
+        "speedup_vs_k1_one_at_a_time": round(k1_ms / batch_ms, 3),
+        "k1_sample": "every %dth request (%d), time scaled by %d/%d" % (k1_stride, len(sel), count, len(sel)),
+        "bit_exact_vs_one_at_a_time": bool(exact and exact_k1),
+        "k_chosen": {str(k): v for k, v in sorted(ks.items())},
+        "cost_model": {"train_requests": train_count, "train_rows": len(X), "final_loss": round(loss, 5),
+                       "heldout_requests": heldout, "heldout_regret": round(t_mlp / t_best - 1, 4),
+                       "heldout_gain_vs_default": round(t_def / t_mlp, 4)},
+        "host_s": {"generate": round(gen_s, 2), "tune": round(tune_s, 2), "train": round(train_s, 2),
+                   "choose": round(choose_s, 2), "plan": round(plan_s, 2)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-products measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
@@ -126,6 +263,7 @@ def main():
     cells = alg_cells_tft(l, len_g, n) + alg_cells_tft(l, len_h, n) + alg_cells_itft(l, n, n, 0)
     alg_bytes = cells * cell_bytes
 
+    _progress("large product: warmup")
     for _ in range(args.warmup):
         T.zx_mul_ss_timed(dg, dh, out, ws=ws)
     torch.cuda.synchronize()
@@ -178,7 +316,12 @@ def main():
             "avg_launch_ms": round(leaf_ms / max(1, launches), 4),
         },
     }
+    del out, ws, dg, dh
+    torch.cuda.empty_cache()
+    if not args.no_batch:
+        line["batch"] = batch_leg(T, torch)
     if not args.no_cpu_baseline:
+        _progress("cpu baseline (oracle sample)")
         line["cpu_baseline"] = cpu_baseline(g, N, l, len_g, n, alg_bytes)
     print(json.dumps(line), flush=True)
 

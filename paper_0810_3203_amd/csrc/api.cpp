@@ -251,6 +251,10 @@ tft_plan *cached_plan(const tft_ring *ring, uint32_t dir, uint32_t l, uint64_t s
 
 }  // namespace
 
+namespace tft {
+int device_error(hipError_t e, const char *where) { return dev_fail(e, where); }
+}  // namespace tft
+
 extern "C" {
 
 const char *tft_last_error(void) { return g_last_error; }

@@ -104,7 +104,8 @@ int upload_group(Group &G) {
     const size_t bi = al(G.items.size() * sizeof(uint4)), bk = al(G.packs.size() * sizeof(PackDesc));
     const size_t b1 = al(G.unpack1.size() * sizeof(UnpackDesc)), b2 = al(G.unpackk.size() * sizeof(UnpackDesc));
     const size_t total = bj + bp + bs + bo + bi + bk + b1 + b2 + 256;
-    if (hipMalloc(&G.dev, total) != hipSuccess) return TFT_E_DEVICE;
+    hipError_t me = hipMalloc(&G.dev, total);
+    if (me != hipSuccess) return device_error(me, "batch: hipMalloc of descriptors");
     char *c = static_cast<char *>(G.dev);
     size_t off = 0;
     hipError_t e = hipSuccess;
@@ -122,7 +123,7 @@ int upload_group(Group &G) {
     G.d_packs = static_cast<PackDesc *>(put(G.packs.data(), G.packs.size() * sizeof(PackDesc), bk));
     G.d_unpack1 = static_cast<UnpackDesc *>(put(G.unpack1.data(), G.unpack1.size() * sizeof(UnpackDesc), b1));
     G.d_unpackk = static_cast<UnpackDesc *>(put(G.unpackk.data(), G.unpackk.size() * sizeof(UnpackDesc), b2));
-    return e == hipSuccess ? TFT_OK : TFT_E_DEVICE;
+    return e == hipSuccess ? TFT_OK : device_error(e, "batch: descriptor upload");
 }
 
 hipError_t run_passes(const Group &G, const std::vector<Pass> &passes, uint32_t *x, hipStream_t st) {
@@ -325,10 +326,14 @@ int tft_batch_plan_execute(tft_batch_plan *plan, void *ws, uint64_t ws_bytes, in
         plan->uploaded = true;
     }
     char *w = static_cast<char *>(ws);
-    if (!use_graph) return run_plan(plan, w, st) == hipSuccess ? TFT_OK : TFT_E_DEVICE;
+    if (!use_graph) {
+        hipError_t e = run_plan(plan, w, st);
+        return e == hipSuccess ? TFT_OK : device_error(e, "batch: launch");
+    }
     if (!plan->exec || plan->graph_ws != ws) {
         // run once eagerly (sets kernel attributes outside capture), then capture
-        if (run_plan(plan, w, st) != hipSuccess) return TFT_E_DEVICE;
+        hipError_t re = run_plan(plan, w, st);
+        if (re != hipSuccess) return device_error(re, "batch: launch");
         if (plan->exec) {
             (void)hipGraphExecDestroy(plan->exec);
             (void)hipGraphDestroy(plan->graph);
@@ -336,7 +341,8 @@ int tft_batch_plan_execute(tft_batch_plan *plan, void *ws, uint64_t ws_bytes, in
             plan->graph = nullptr;
         }
         hipStream_t cs;
-        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return TFT_E_DEVICE;
+        hipError_t ce = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (ce != hipSuccess) return device_error(ce, "batch: hipStreamCreateWithFlags");
         hipError_t e = hipStreamSynchronize(st);
         if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
@@ -346,11 +352,12 @@ int tft_batch_plan_execute(tft_batch_plan *plan, void *ws, uint64_t ws_bytes, in
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
         (void)hipStreamDestroy(cs);
-        if (e != hipSuccess) return TFT_E_DEVICE;
+        if (e != hipSuccess) return device_error(e, "batch: graph capture");
         plan->graph_ws = ws;
         return TFT_OK;  // the eager run already produced this call's results
     }
-    return hipGraphLaunch(plan->exec, st) == hipSuccess ? TFT_OK : TFT_E_DEVICE;
+    hipError_t ge = hipGraphLaunch(plan->exec, st);
+    return ge == hipSuccess ? TFT_OK : device_error(ge, "batch: hipGraphLaunch");
 }
 
 void tft_batch_plan_destroy(tft_batch_plan *plan) {

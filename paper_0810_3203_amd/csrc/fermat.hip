@@ -12,6 +12,8 @@ namespace tft {
 namespace {
 
 constexpr uint32_t kLdsBudget = 160u * 1024u;
+// work-items per grid dimension of one launch (the dispatch packet holds 32-bit sizes)
+constexpr uint32_t kMaxGridX = 0xFFFFFFFFu;
 constexpr uint32_t kLeafStaticLds = 0u;  // no static LDS in fermat_leaf_kernel
 
 // Copy leaf cells [0, n) between the global array (cell-contiguous limbs) and
@@ -318,9 +320,9 @@ __device__ __forceinline__ void pointwise_body(const uint32_t *a, uint32_t ta, c
 template <int S, int C>
 __global__ void __launch_bounds__(256) fermat_pointwise_kernel(const uint32_t *__restrict__ a,
                                                                const uint32_t *__restrict__ b, uint32_t *c,
-                                                               uint64_t cap, uint32_t scale_e) {
+                                                               uint64_t cap, uint32_t scale_e, uint32_t base) {
     constexpr int W = S * C;
-    const uint64_t i = blockIdx.x;
+    const uint64_t i = (uint64_t)base + blockIdx.x;
     pointwise_body<S, C>(a + i * W, a[cap * W + i], b + i * W, b[cap * W + i], c + i * W, c + cap * W + i, scale_e);
 }
 
@@ -408,9 +410,16 @@ hipError_t leaf_launch(uint32_t nwaves, uint32_t njobs, uint32_t lds_cells, cons
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL((fermat_leaf_kernel<S, C>), dim3(njobs), dim3(64 * nwaves), lds, st, jobs, progs, steps, ops,
-                       x, cap, ord_mask, lds_cells, job_offset);
-    return hipGetLastError();
+    // a launch covers at most 2^32 - 1 work-items per grid dimension
+    const uint32_t per = kMaxGridX / (64 * nwaves);
+    for (uint32_t j0 = 0; j0 < njobs; j0 += per) {
+        const uint32_t nb = njobs - j0 < per ? njobs - j0 : per;
+        hipLaunchKernelGGL((fermat_leaf_kernel<S, C>), dim3(nb), dim3(64 * nwaves), lds, st, jobs, progs, steps, ops,
+                           x, cap, ord_mask, lds_cells, job_offset + j0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <class KernelT>
@@ -431,9 +440,15 @@ hipError_t pointwise_launch(uint64_t n, const uint32_t *a, const uint32_t *b, ui
     static bool attr = false;
     hipError_t e = pointwise_attr(&fermat_pointwise_kernel<S, C>, lds, attr);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((fermat_pointwise_kernel<S, C>), dim3((uint32_t)n), dim3(pw_threads(W)), lds, st, a, b, c,
-                       cap, scale_e);
-    return hipGetLastError();
+    const uint64_t per = kMaxGridX / pw_threads(W);
+    for (uint64_t i0 = 0; i0 < n; i0 += per) {
+        const uint64_t nb = n - i0 < per ? n - i0 : per;
+        hipLaunchKernelGGL((fermat_pointwise_kernel<S, C>), dim3((uint32_t)nb), dim3(pw_threads(W)), lds, st, a, b,
+                           c, cap, scale_e, (uint32_t)i0);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <int S, int C>
@@ -444,9 +459,15 @@ hipError_t pointwise_items_launch(uint64_t nitems, uint32_t *x, uint64_t cap, co
     static bool attr = false;
     hipError_t e = pointwise_attr(&fermat_pointwise_items_kernel<S, C>, lds, attr);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((fermat_pointwise_items_kernel<S, C>), dim3((uint32_t)nitems), dim3(pw_threads(W)), lds, st,
-                       x, cap, items);
-    return hipGetLastError();
+    const uint64_t per = kMaxGridX / pw_threads(W);
+    for (uint64_t i0 = 0; i0 < nitems; i0 += per) {
+        const uint64_t nb = nitems - i0 < per ? nitems - i0 : per;
+        hipLaunchKernelGGL((fermat_pointwise_items_kernel<S, C>), dim3((uint32_t)nb), dim3(pw_threads(W)), lds, st,
+                           x, cap, items + i0);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace

@@ -34,6 +34,9 @@ hipError_t launch_fermat_unpack(uint32_t W, const UnpackDesc *descs, uint32_t nd
 // Largest LDS bytes one workgroup may use.
 uint32_t lds_budget_bytes();
 
+// Records a failed HIP call for tft_last_error; returns TFT_E_DEVICE.
+int device_error(hipError_t e, const char *where);
+
 // LDS bytes of one Fermat cell inside a leaf workgroup (padded chunk layout plus top word).
 uint32_t fermat_lds_cell_bytes(uint32_t W);
 

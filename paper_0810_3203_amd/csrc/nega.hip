@@ -15,6 +15,8 @@ namespace tft {
 namespace {
 
 constexpr uint32_t kLdsBudget = 160u * 1024u;
+// work-items per grid dimension of one launch (the dispatch packet holds 32-bit sizes)
+constexpr uint32_t kMaxGridX = 0xFFFFFFFFu;
 
 __device__ __forceinline__ uint64_t madd(uint64_t a, uint64_t b, uint64_t m) {
     const uint64_t s = a + b;
@@ -292,9 +294,15 @@ hipError_t nega_leaf_launch(uint64_t m, uint32_t nwaves, uint32_t njobs, uint32_
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL((nega_leaf_kernel<S, R>), dim3(njobs), dim3(64 * nwaves), lds, st, jobs, progs, steps, ops, x,
-                       m, ord_mask, job_offset);
-    return hipGetLastError();
+    const uint32_t per = kMaxGridX / (64 * nwaves);
+    for (uint32_t j0 = 0; j0 < njobs; j0 += per) {
+        const uint32_t nb = njobs - j0 < per ? njobs - j0 : per;
+        hipLaunchKernelGGL((nega_leaf_kernel<S, R>), dim3(nb), dim3(64 * nwaves), lds, st, jobs, progs, steps, ops, x,
+                           m, ord_mask, job_offset + j0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <int K>
@@ -313,8 +321,15 @@ hipError_t nega_pw_launch(uint64_t m, uint64_t n, const uint64_t *a, const uint6
     thr = thr < 64 ? 64 : (thr > 256 ? 256 : thr);
     thr = (thr + 63) / 64 * 64;
     if ((uint32_t)K > thr * NP_COLS) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((nega_pointwise_kernel<K>), dim3((uint32_t)n), dim3(thr), 0, st, a, b, c, m, minv, cfac);
-    return hipGetLastError();
+    const uint64_t per = kMaxGridX / thr;
+    for (uint64_t i0 = 0; i0 < n; i0 += per) {
+        const uint64_t nb = n - i0 < per ? n - i0 : per;
+        hipLaunchKernelGGL((nega_pointwise_kernel<K>), dim3((uint32_t)nb), dim3(thr), 0, st, a + i0 * K, b + i0 * K,
+                           c + i0 * K, m, minv, cfac);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace

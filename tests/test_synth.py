@@ -1,6 +1,7 @@
 """Seeded input generators: SplitMix64 test vector and workload shapes."""
 
 import numpy as np
+import pytest
 
 from synth import SplitMix64
 from synth import workloads as wl
@@ -49,3 +50,24 @@ def test_batch_lengths_in_range():
     g, h = wl.batch_request(3)
     assert (g.shape[0], h.shape[0]) == wl.batch_lengths(4)[3]
     assert g.shape[1] == 32 and int(g[:, 31].max()) < (1 << 8)
+
+
+def test_device_generator_matches_numpy():
+    torch = pytest.importorskip("torch")
+    from synth import device as dev
+    from synth.splitmix import SplitMix64
+    s = SplitMix64(1234567)
+    ref = s.take(1000)
+    got = dev.draws(torch, 1234567, 0, 1000, "cpu").numpy().view(np.uint64)
+    assert np.array_equal(got, ref)
+    for i in (0, 5):
+        g, h = wl.batch_request(i, len_lo=10, len_hi=300)
+        dg, dh = dev.batch_request(torch, i, "cpu", len_lo=10, len_hi=300)
+        assert np.array_equal(dg.numpy().view(np.uint32), g)
+        assert np.array_equal(dh.numpy().view(np.uint32), h)
+    for bits in (32, 64, 96, 1000):
+        s = SplitMix64(99)
+        s.take(3)
+        ref = wl.random_ints(s, 17, bits)
+        got = dev.ints(torch, 99, 3, 17, bits, "cpu").numpy().view(np.uint32)
+        assert np.array_equal(got, ref), bits
