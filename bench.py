@@ -234,6 +234,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-products measurement")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run three plain 1 GiB device copies (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
@@ -324,6 +326,12 @@ def main():
         _progress("cpu baseline (oracle sample)")
         line["cpu_baseline"] = cpu_baseline(g, N, l, len_g, n, alg_bytes)
     print(json.dumps(line), flush=True)
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

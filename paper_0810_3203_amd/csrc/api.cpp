@@ -222,7 +222,8 @@ int plan_run(tft_plan *p, void *x, hipStream_t st, LaunchTimer *lt = nullptr) {
         if (lt && (e = lt->mark(st, true)) != hipSuccess) return dev_fail(e, "timer");
         if (p->ring.kind == TFT_RING_FERMAT)
             e = launch_fermat_leaf(p->ring.N / 32, p->nwaves[i], pd.job_count, pd.max_len, p->d_jobs, pd.job_begin,
-                                   p->d_progs, p->d_steps, p->d_ops, static_cast<uint32_t *>(x), cap, ord_mask, st);
+                                   p->d_progs, p->d_steps, p->d_ops, static_cast<uint32_t *>(x), cap, ord_mask,
+                                   pd.opmask, st);
         else
             e = launch_nega_leaf(p->ring.K, p->ring.m, p->nwaves[i], pd.job_count, pd.max_len, p->d_jobs,
                                  pd.job_begin, p->d_progs, p->d_steps, p->d_ops, static_cast<uint64_t *>(x), ord_mask,

@@ -35,7 +35,7 @@ uint32_t fermat_max_leaf_log2(uint32_t W) {
 }
 
 struct Pass {
-    uint32_t job_begin, job_count, max_len, nwaves;
+    uint32_t job_begin, job_count, max_len, nwaves, opmask;
 };
 
 struct Group {
@@ -130,7 +130,7 @@ hipError_t run_passes(const Group &G, const std::vector<Pass> &passes, uint32_t 
     const uint32_t ord_mask = 64u * G.W - 1u;
     for (const Pass &p : passes) {
         hipError_t e = launch_fermat_leaf(G.W, p.nwaves, p.job_count, p.max_len, G.d_jobs, p.job_begin, G.d_progs,
-                                          G.d_steps, G.d_ops, x, G.cap, ord_mask, st);
+                                          G.d_steps, G.d_ops, x, G.cap, ord_mask, p.opmask, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -233,7 +233,7 @@ int tft_batch_plan_create(const tft_zx_request *reqs, uint32_t count, uint64_t m
                 for (const auto &lst : lists)
                     for (const auto *s : lst) np = std::max(np, s->first.passes.size());
                 for (size_t p = 0; p < np; p++) {
-                    Pass ps{(uint32_t)G.jobs.size(), 0, 0, 1};
+                    Pass ps{(uint32_t)G.jobs.size(), 0, 0, 1, 0};
                     uint32_t max_ops = 0;
                     for (size_t li = 0; li < lists.size(); li++) {
                         for (size_t q = 0; q < lists[li].size(); q++) {
@@ -247,6 +247,7 @@ int tft_batch_plan_create(const tft_zx_request *reqs, uint32_t count, uint64_t m
                                 G.jobs.push_back(jb);
                             }
                             ps.max_len = std::max(ps.max_len, pd.max_len);
+                            ps.opmask |= pd.opmask;
                             max_ops = std::max(max_ops, pd.max_ops);
                         }
                     }

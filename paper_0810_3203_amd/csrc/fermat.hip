@@ -87,13 +87,23 @@ __device__ __forceinline__ void copy_cells(uint32_t *sm, uint32_t *x, const Job 
     }
 }
 
-template <int S, int C>
-__global__ void __launch_bounds__(512) fermat_leaf_kernel(const Job *__restrict__ jobs,
-                                                           const LeafProg *__restrict__ progs,
-                                                           const LeafStep *__restrict__ steps,
-                                                           const LeafOp *__restrict__ ops, uint32_t *__restrict__ x,
-                                                           uint64_t cap, uint32_t ord_mask, uint32_t lds_cells,
-                                                           uint32_t job_offset) {
+// Base-case sets a leaf kernel is compiled for.  Keeping the rare boundary
+// cases out of the hot kernels keeps their register allocation within 256
+// VGPRs (no spills) for the largest elements.
+enum LeafSet : int { SET_TFT = 0, SET_ITFT = 1, SET_ALL = 2 };
+constexpr uint32_t kTftOps = (1u << OP_T22) | (1u << OP_T21) | (1u << OP_T12);
+constexpr uint32_t kItftOps = (1u << OP_I2) | (1u << OP_I1F1Z2) | (1u << OP_I1F0Z2) | (1u << OP_I1F0Z1);
+
+template <int V>
+constexpr bool set_has(uint32_t code) {
+    return V == SET_ALL || (V == SET_TFT ? ((kTftOps >> code) & 1u) : ((kItftOps >> code) & 1u));
+}
+
+template <int S, int C, int V>
+__device__ __forceinline__ void leaf_body(const Job *__restrict__ jobs, const LeafProg *__restrict__ progs,
+                                          const LeafStep *__restrict__ steps, const LeafOp *__restrict__ ops,
+                                          uint32_t *__restrict__ x, uint64_t cap, uint32_t ord_mask,
+                                          uint32_t lds_cells, uint32_t job_offset) {
     using F = FChunk<S, C>;
     constexpr int W = F::W;
     constexpr uint32_t G = 64 / S;
@@ -123,19 +133,39 @@ __global__ void __launch_bounds__(512) fermat_leaf_kernel(const Job *__restrict_
                 uint32_t *x0 = sm + i0 * F::ESZ, *x1 = sm + i1 * F::ESZ;
                 uint32_t *t0 = stop + i0, *t1 = stop + i1;
                 switch (code) {
-                    case OP_T22: B.t22(x0, x1, t0, t1, e); break;
-                    case OP_T21: B.t21(x0, x1, t0, t1, e); break;
-                    case OP_T12: B.add2(x0, x1, t0, t1); break;
-                    case OP_I2: B.i2(x0, x1, t0, t1, (0u - e) & ord_mask); break;
-                    case OP_I1F1Z2: B.i1f1(x0, x1, t0, t1, e, true); break;
-                    case OP_I1F1Z1: B.i1f1(x0, x1, t0, t1, e, false); break;
-                    case OP_I1F0Z2: B.dbl_sub(x0, x1, t0, t1); break;
-                    case OP_I1F0Z1: B.dbl_sub(x0, nullptr, t0, nullptr); break;
-                    case OP_I0Z2:
-                        B.add2(x0, x1, t0, t1);
-                        B.scale(x0, t0, ord_mask);  // 2^(2N-1) = 1/2
+                    case OP_T22:
+                        if constexpr (set_has<V>(OP_T22)) B.t22(x0, x1, t0, t1, e);
                         break;
-                    case OP_I0Z1: B.scale(x0, t0, ord_mask); break;
+                    case OP_T21:
+                        if constexpr (set_has<V>(OP_T21)) B.t21(x0, x1, t0, t1, e);
+                        break;
+                    case OP_T12:
+                        if constexpr (set_has<V>(OP_T12)) B.add2(x0, x1, t0, t1);
+                        break;
+                    case OP_I2:
+                        if constexpr (set_has<V>(OP_I2)) B.i2(x0, x1, t0, t1, (0u - e) & ord_mask);
+                        break;
+                    case OP_I1F1Z2:
+                        if constexpr (set_has<V>(OP_I1F1Z2)) B.i1f1(x0, x1, t0, t1, e, true);
+                        break;
+                    case OP_I1F1Z1:
+                        if constexpr (set_has<V>(OP_I1F1Z1)) B.i1f1(x0, x1, t0, t1, e, false);
+                        break;
+                    case OP_I1F0Z2:
+                        if constexpr (set_has<V>(OP_I1F0Z2)) B.dbl_sub(x0, x1, t0, t1);
+                        break;
+                    case OP_I1F0Z1:
+                        if constexpr (set_has<V>(OP_I1F0Z1)) B.dbl_sub(x0, nullptr, t0, nullptr);
+                        break;
+                    case OP_I0Z2:
+                        if constexpr (set_has<V>(OP_I0Z2)) {
+                            B.add2(x0, x1, t0, t1);
+                            B.scale(x0, t0, ord_mask);  // 2^(2N-1) = 1/2
+                        }
+                        break;
+                    case OP_I0Z1:
+                        if constexpr (set_has<V>(OP_I0Z1)) B.scale(x0, t0, ord_mask);
+                        break;
                     default: break;
                 }
             }
@@ -145,6 +175,16 @@ __global__ void __launch_bounds__(512) fermat_leaf_kernel(const Job *__restrict_
 
     copy_cells<F, false>(sm, x, J, J.nstore, tid, nthr);
     for (uint32_t t = tid; t < J.nstore; t += nthr) x[cap * W + J.base + (uint64_t)t * J.stride] = stop[t];
+}
+
+template <int S, int C, int V>
+__global__ void __launch_bounds__(512) fermat_leaf_kernel(const Job *__restrict__ jobs,
+                                                           const LeafProg *__restrict__ progs,
+                                                           const LeafStep *__restrict__ steps,
+                                                           const LeafOp *__restrict__ ops, uint32_t *__restrict__ x,
+                                                           uint64_t cap, uint32_t ord_mask, uint32_t lds_cells,
+                                                           uint32_t job_offset) {
+    leaf_body<S, C, V>(jobs, progs, steps, ops, x, cap, ord_mask, lds_cells, job_offset);
 }
 
 // ---------------------------------------------------------------------------
@@ -396,15 +436,16 @@ __global__ void fermat_unpackk_kernel(const UnpackDesc *__restrict__ descs, Unpa
     }
 }
 
-template <int S, int C>
-hipError_t leaf_launch(uint32_t nwaves, uint32_t njobs, uint32_t lds_cells, const Job *jobs, uint32_t job_offset,
-                       const LeafProg *progs, const LeafStep *steps, const LeafOp *ops, uint32_t *x, uint64_t cap,
-                       uint32_t ord_mask, hipStream_t st) {
+template <int S, int C, int V>
+hipError_t leaf_launch_set(uint32_t nwaves, uint32_t njobs, uint32_t lds_cells, const Job *jobs, uint32_t job_offset,
+                           const LeafProg *progs, const LeafStep *steps, const LeafOp *ops, uint32_t *x, uint64_t cap,
+                           uint32_t ord_mask, hipStream_t st) {
     const size_t lds = (size_t)lds_cells * (FChunk<S, C>::ESZ + 1) * 4;
     if (lds > kLdsBudget - kLeafStaticLds) return hipErrorInvalidValue;
+    auto kern = &fermat_leaf_kernel<S, C, V>;
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fermat_leaf_kernel<S, C>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)(kLdsBudget - kLeafStaticLds));
         if (e != hipSuccess) return e;
@@ -414,12 +455,26 @@ hipError_t leaf_launch(uint32_t nwaves, uint32_t njobs, uint32_t lds_cells, cons
     const uint32_t per = kMaxGridX / (64 * nwaves);
     for (uint32_t j0 = 0; j0 < njobs; j0 += per) {
         const uint32_t nb = njobs - j0 < per ? njobs - j0 : per;
-        hipLaunchKernelGGL((fermat_leaf_kernel<S, C>), dim3(nb), dim3(64 * nwaves), lds, st, jobs, progs, steps, ops,
-                           x, cap, ord_mask, lds_cells, job_offset + j0);
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(64 * nwaves), lds, st, jobs, progs, steps, ops, x, cap, ord_mask,
+                           lds_cells, job_offset + j0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+template <int S, int C>
+hipError_t leaf_launch(uint32_t nwaves, uint32_t njobs, uint32_t lds_cells, const Job *jobs, uint32_t job_offset,
+                       const LeafProg *progs, const LeafStep *steps, const LeafOp *ops, uint32_t *x, uint64_t cap,
+                       uint32_t ord_mask, uint32_t opmask, hipStream_t st) {
+    if ((opmask & ~kTftOps) == 0u)
+        return leaf_launch_set<S, C, SET_TFT>(nwaves, njobs, lds_cells, jobs, job_offset, progs, steps, ops, x, cap,
+                                              ord_mask, st);
+    if ((opmask & ~kItftOps) == 0u)
+        return leaf_launch_set<S, C, SET_ITFT>(nwaves, njobs, lds_cells, jobs, job_offset, progs, steps, ops, x, cap,
+                                               ord_mask, st);
+    return leaf_launch_set<S, C, SET_ALL>(nwaves, njobs, lds_cells, jobs, job_offset, progs, steps, ops, x, cap,
+                                          ord_mask, st);
 }
 
 template <class KernelT>
@@ -500,10 +555,10 @@ uint32_t fermat_lds_cell_bytes(uint32_t W) {
 
 hipError_t launch_fermat_leaf(uint32_t W, uint32_t nwaves, uint32_t njobs, uint32_t lds_cells, const Job *jobs,
                               uint32_t job_offset, const LeafProg *progs, const LeafStep *steps, const LeafOp *ops,
-                              uint32_t *x, uint64_t cap, uint32_t ord_mask, hipStream_t st) {
+                              uint32_t *x, uint64_t cap, uint32_t ord_mask, uint32_t opmask, hipStream_t st) {
     if (njobs == 0) return hipSuccess;
     TFT_FERMAT_DISPATCH(W, leaf_launch, nwaves, njobs, lds_cells, jobs, job_offset, progs, steps, ops, x, cap,
-                        ord_mask, st)
+                        ord_mask, opmask, st)
 }
 
 hipError_t launch_fermat_pointwise(uint32_t W, uint64_t n, const uint32_t *a, const uint32_t *b, uint32_t *c,

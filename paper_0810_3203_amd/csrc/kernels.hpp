@@ -8,9 +8,10 @@
 namespace tft {
 
 // Leaf workgroups for one pass of a Fermat-ring transform.
+// opmask: BaseOp bits the pass's programs use; selects a kernel compiled for that set of base cases.
 hipError_t launch_fermat_leaf(uint32_t W, uint32_t nwaves, uint32_t njobs, uint32_t lds_cells, const Job *jobs,
                               uint32_t job_offset, const LeafProg *progs, const LeafStep *steps, const LeafOp *ops,
-                              uint32_t *x, uint64_t cap, uint32_t ord_mask, hipStream_t st);
+                              uint32_t *x, uint64_t cap, uint32_t ord_mask, uint32_t opmask, hipStream_t st);
 
 // c_i = a_i b_i 2^scale_e (scale_e = -scale_log2 mod 2N) for i < n, cell arrays of capacity cap.
 hipError_t launch_fermat_pointwise(uint32_t W, uint64_t n, const uint32_t *a, const uint32_t *b, uint32_t *c,

@@ -138,13 +138,16 @@ struct Builder {
         P.step_count = 0;
         P.len = len;
         P.max_ops = 0;
+        uint32_t opmask = 0;
         for (auto &st : steps) {
             if (st.empty()) continue;
             // group equal opcodes so that the segments of one wave mostly agree
             std::stable_sort(st.begin(), st.end(), [](const SymOp &a, const SymOp &b) { return a.code < b.code; });
             LeafStep ls{(uint32_t)S->ops.size(), (uint32_t)st.size()};
-            for (const SymOp &o : st)
+            for (const SymOp &o : st) {
                 S->ops.push_back({o.code | (o.i0 << 4) | (o.i1 << 18), (o.b & 0xFFFFFFu) | (o.alog << 24)});
+                opmask |= 1u << o.code;
+            }
             S->steps.push_back(ls);
             P.step_count++;
             P.max_ops = std::max(P.max_ops, ls.op_count);
@@ -152,6 +155,7 @@ struct Builder {
         uint32_t id = (uint32_t)S->progs.size();
         S->progs.push_back(P);
         S->prog_base_cases.push_back(nbase);
+        S->prog_opmask.push_back(opmask);
         cache[key] = id;
         return id;
     }
@@ -251,9 +255,11 @@ Schedule build_schedule(uint32_t direction, uint32_t l, uint32_t ord, uint64_t s
         pd.job_count = (uint32_t)jobs.size();
         pd.max_len = 0;
         pd.max_ops = 0;
+        pd.opmask = 0;
         for (const Job &j : jobs) {
             pd.max_len = std::max(pd.max_len, S.progs[j.prog].len);
             pd.max_ops = std::max(pd.max_ops, S.progs[j.prog].max_ops);
+            pd.opmask |= S.prog_opmask[j.prog];
             S.base_cases += S.prog_base_cases[j.prog];
         }
         S.jobs.insert(S.jobs.end(), jobs.begin(), jobs.end());

@@ -24,6 +24,7 @@ struct PassDesc {
     uint32_t job_count;
     uint32_t max_len;  // largest leaf length among the pass's jobs
     uint32_t max_ops;  // largest step width among the pass's programs
+    uint32_t opmask;   // bit c set if a job of the pass runs base case c (BaseOp)
 };
 
 struct Schedule {
@@ -37,6 +38,7 @@ struct Schedule {
     std::vector<LeafStep> steps;
     std::vector<LeafOp> ops;
     std::vector<uint32_t> prog_base_cases;  // base cases per program (no-ops included)
+    std::vector<uint32_t> prog_opmask;      // BaseOp bits used per program
     uint64_t base_cases = 0;
 };
 
