@@ -208,7 +208,7 @@ struct LaunchTimer {
     }
 };
 
-int plan_run(tft_plan *p, void *x, hipStream_t st, LaunchTimer *lt = nullptr) {
+int plan_run(tft_plan *p, void *x, hipStream_t st, LaunchTimer *lt = nullptr, bool transposed = false) {
     std::lock_guard<std::mutex> lk(p->mu);
     for (const PassDesc &pd : p->sched.passes)
         if ((uint64_t)pd.max_len * cell_lds_bytes(&p->ring) > lds_budget_bytes()) return TFT_E_UNSUPPORTED;
@@ -223,7 +223,7 @@ int plan_run(tft_plan *p, void *x, hipStream_t st, LaunchTimer *lt = nullptr) {
         if (p->ring.kind == TFT_RING_FERMAT)
             e = launch_fermat_leaf(p->ring.N / 32, p->nwaves[i], pd.job_count, pd.max_len, p->d_jobs, pd.job_begin,
                                    p->d_progs, p->d_steps, p->d_ops, static_cast<uint32_t *>(x), cap, ord_mask,
-                                   pd.opmask, st);
+                                   pd.opmask, transposed, st);
         else
             e = launch_nega_leaf(p->ring.K, p->ring.m, p->nwaves[i], pd.job_count, pd.max_len, p->d_jobs,
                                  pd.job_begin, p->d_progs, p->d_steps, p->d_ops, static_cast<uint64_t *>(x), ord_mask,
@@ -379,7 +379,7 @@ int pointwise_mul(const tft_ring *ring, uint64_t n, const void *a, const void *b
         const uint32_t e = (uint32_t)((ord - (scale_log2 % ord)) % ord);
         return hip_status(launch_fermat_pointwise(ring->N / 32, n, static_cast<const uint32_t *>(a),
                                                   static_cast<const uint32_t *>(b), static_cast<uint32_t *>(c), cap,
-                                                  e, hs));
+                                                  e, false, hs));
     }
     return hip_status(launch_nega_pointwise(ring->K, ring->m, n, static_cast<const uint64_t *>(a),
                                             static_cast<const uint64_t *>(b), static_cast<uint64_t *>(c),
@@ -429,24 +429,24 @@ static int ss_run(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uin
     hipError_t e = mark(0);
     const PackDesc dg{g, len_g, 0, sh.zg, g_limbs, sh.k, sh.ws, 0};
     const PackDesc dh{h, len_h, 0, sh.zh, h_limbs, sh.k, sh.ws, 0};
-    if (e == hipSuccess) e = launch_fermat_pack(sh.W, nullptr, 1, dg, sh.zg, A, sh.L, hs);
-    if (e == hipSuccess) e = launch_fermat_pack(sh.W, nullptr, 1, dh, sh.zh, B, sh.L, hs);
+    if (e == hipSuccess) e = launch_fermat_pack(sh.W, nullptr, 1, dg, sh.zg, A, sh.L, true, hs);
+    if (e == hipSuccess) e = launch_fermat_pack(sh.W, nullptr, 1, dh, sh.zh, B, sh.L, true, hs);
     if (e == hipSuccess) e = mark(1);
     if (e != hipSuccess) st = dev_fail(e, "pack");
-    if (!st) st = plan_run(pg, A, hs, ltp);
+    if (!st) st = plan_run(pg, A, hs, ltp, true);
     if (!st && (e = mark(2)) != hipSuccess) st = dev_fail(e, "event");
-    if (!st) st = plan_run(ph, B, hs, ltp);
+    if (!st) st = plan_run(ph, B, hs, ltp, true);
     if (!st && (e = mark(3)) != hipSuccess) st = dev_fail(e, "event");
     if (!st) {
-        e = launch_fermat_pointwise(sh.W, sh.n, A, B, A, sh.L, (uint32_t)((2 * sh.N - sh.l) % (2 * sh.N)), hs);
+        e = launch_fermat_pointwise(sh.W, sh.n, A, B, A, sh.L, (uint32_t)((2 * sh.N - sh.l) % (2 * sh.N)), true, hs);
         if (e == hipSuccess) e = mark(4);
         if (e != hipSuccess) st = dev_fail(e, "pointwise");
     }
-    if (!st) st = plan_run(pi, A, hs, ltp);
+    if (!st) st = plan_run(pi, A, hs, ltp, true);
     if (!st && (e = mark(5)) != hipSuccess) st = dev_fail(e, "event");
     if (!st) {
         const UnpackDesc du{out, len_g + len_h - 1, 0, sh.n, out_limbs, sh.k, sh.ws, 0};
-        e = launch_fermat_unpack(sh.W, nullptr, 1, du, len_g + len_h - 1, out_limbs, sh.k > 1, A, sh.L, hs);
+        e = launch_fermat_unpack(sh.W, nullptr, 1, du, len_g + len_h - 1, out_limbs, sh.k > 1, A, sh.L, true, hs);
         if (e == hipSuccess) e = mark(6);
         if (e != hipSuccess) st = dev_fail(e, "unpack");
     }

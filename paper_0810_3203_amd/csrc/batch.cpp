@@ -130,7 +130,7 @@ hipError_t run_passes(const Group &G, const std::vector<Pass> &passes, uint32_t 
     const uint32_t ord_mask = 64u * G.W - 1u;
     for (const Pass &p : passes) {
         hipError_t e = launch_fermat_leaf(G.W, p.nwaves, p.job_count, p.max_len, G.d_jobs, p.job_begin, G.d_progs,
-                                          G.d_steps, G.d_ops, x, G.cap, ord_mask, p.opmask, st);
+                                          G.d_steps, G.d_ops, x, G.cap, ord_mask, p.opmask, true, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -142,16 +142,18 @@ hipError_t run_plan(tft_batch_plan *P, char *ws, hipStream_t st) {
     for (const Chunk &C : P->chunks) {
         for (const Group &G : C.groups) {
             uint32_t *x = reinterpret_cast<uint32_t *>(ws + G.ws_offset);
-            hipError_t e = launch_fermat_pack(G.W, G.d_packs, (uint32_t)G.packs.size(), np, G.max_z, x, G.cap, st);
+            hipError_t e =
+                launch_fermat_pack(G.W, G.d_packs, (uint32_t)G.packs.size(), np, G.max_z, x, G.cap, true, st);
             if (e == hipSuccess) e = run_passes(G, G.p1, x, st);
-            if (e == hipSuccess) e = launch_fermat_pointwise_items(G.W, G.items.size(), x, G.cap, G.d_items, st);
+            if (e == hipSuccess)
+                e = launch_fermat_pointwise_items(G.W, G.items.size(), x, G.cap, G.d_items, true, st);
             if (e == hipSuccess) e = run_passes(G, G.p2, x, st);
             if (e == hipSuccess && !G.unpack1.empty())
                 e = launch_fermat_unpack(G.W, G.d_unpack1, (uint32_t)G.unpack1.size(), nu, G.max_len1, G.max_ol1,
-                                         false, x, G.cap, st);
+                                         false, x, G.cap, true, st);
             if (e == hipSuccess && !G.unpackk.empty())
                 e = launch_fermat_unpack(G.W, G.d_unpackk, (uint32_t)G.unpackk.size(), nu, G.max_lenk, G.max_olk,
-                                         true, x, G.cap, st);
+                                         true, x, G.cap, true, st);
             if (e != hipSuccess) return e;
         }
     }

@@ -5,187 +5,13 @@
 
 #include "desc.hpp"
 #include "fermat_dev.hpp"
+#include "fermat_leaf.hpp"
 #include "kernels.hpp"
 
 namespace tft {
 
 namespace {
 
-constexpr uint32_t kLdsBudget = 160u * 1024u;
-// work-items per grid dimension of one launch (the dispatch packet holds 32-bit sizes)
-constexpr uint32_t kMaxGridX = 0xFFFFFFFFu;
-constexpr uint32_t kLeafStaticLds = 0u;  // no static LDS in fermat_leaf_kernel
-
-// Copy leaf cells [0, n) between the global array (cell-contiguous limbs) and
-// LDS (cells ESZ dwords apart, limb k at F::addr(k)).  Each thread keeps
-// CB 16-byte global accesses in flight before touching LDS.
-constexpr int CB = 8;
-
-template <class F, bool IN>
-__device__ __forceinline__ void copy_cells(uint32_t *sm, uint32_t *x, const Job &J, uint32_t n, uint32_t tid,
-                                           uint32_t nthr) {
-    constexpr int W = F::W;
-    if constexpr (W % 4 == 0) {
-        constexpr uint32_t WQ = W / 4;
-        const uint32_t total = n * WQ;
-        for (uint32_t q0 = tid; q0 < total; q0 += nthr * CB) {
-            uint4 v[CB];
-            if (IN) {
-#pragma unroll
-                for (int b = 0; b < CB; ++b) {
-                    const uint32_t q = q0 + b * nthr;
-                    if (q < total) {
-                        const uint32_t cell = q / WQ, off = q % WQ;
-                        v[b] = reinterpret_cast<const uint4 *>(x + (J.base + (uint64_t)cell * J.stride) * W)[off];
-                    }
-                }
-#pragma unroll
-                for (int b = 0; b < CB; ++b) {
-                    const uint32_t q = q0 + b * nthr;
-                    if (q < total) {
-                        const uint32_t cell = q / WQ, k = (q % WQ) * 4u;
-                        uint32_t *s = sm + cell * F::ESZ;
-                        s[F::addr(k)] = v[b].x;
-                        s[F::addr(k + 1)] = v[b].y;
-                        s[F::addr(k + 2)] = v[b].z;
-                        s[F::addr(k + 3)] = v[b].w;
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int b = 0; b < CB; ++b) {
-                    const uint32_t q = q0 + b * nthr;
-                    if (q < total) {
-                        const uint32_t cell = q / WQ, k = (q % WQ) * 4u;
-                        const uint32_t *s = sm + cell * F::ESZ;
-                        v[b].x = s[F::addr(k)];
-                        v[b].y = s[F::addr(k + 1)];
-                        v[b].z = s[F::addr(k + 2)];
-                        v[b].w = s[F::addr(k + 3)];
-                    }
-                }
-#pragma unroll
-                for (int b = 0; b < CB; ++b) {
-                    const uint32_t q = q0 + b * nthr;
-                    if (q < total) {
-                        const uint32_t cell = q / WQ, off = q % WQ;
-                        reinterpret_cast<uint4 *>(x + (J.base + (uint64_t)cell * J.stride) * W)[off] = v[b];
-                    }
-                }
-            }
-        }
-    } else {
-        const uint32_t total = n * W;
-        for (uint32_t q = tid; q < total; q += nthr) {
-            const uint32_t cell = q / W, off = q % W;
-            uint32_t *g = x + (J.base + (uint64_t)cell * J.stride) * W + off;
-            if (IN)
-                sm[cell * F::ESZ + F::addr(off)] = *g;
-            else
-                *g = sm[cell * F::ESZ + F::addr(off)];
-        }
-    }
-}
-
-// Base-case sets a leaf kernel is compiled for.  Keeping the rare boundary
-// cases out of the hot kernels keeps their register allocation within 256
-// VGPRs (no spills) for the largest elements.
-enum LeafSet : int { SET_TFT = 0, SET_ITFT = 1, SET_ALL = 2 };
-constexpr uint32_t kTftOps = (1u << OP_T22) | (1u << OP_T21) | (1u << OP_T12);
-constexpr uint32_t kItftOps = (1u << OP_I2) | (1u << OP_I1F1Z2) | (1u << OP_I1F0Z2) | (1u << OP_I1F0Z1);
-
-template <int V>
-constexpr bool set_has(uint32_t code) {
-    return V == SET_ALL || (V == SET_TFT ? ((kTftOps >> code) & 1u) : ((kItftOps >> code) & 1u));
-}
-
-template <int S, int C, int V>
-__device__ __forceinline__ void leaf_body(const Job *__restrict__ jobs, const LeafProg *__restrict__ progs,
-                                          const LeafStep *__restrict__ steps, const LeafOp *__restrict__ ops,
-                                          uint32_t *__restrict__ x, uint64_t cap, uint32_t ord_mask,
-                                          uint32_t lds_cells, uint32_t job_offset) {
-    using F = FChunk<S, C>;
-    constexpr int W = F::W;
-    constexpr uint32_t G = 64 / S;
-    extern __shared__ uint32_t sm[];
-    uint32_t *stop = sm + (size_t)lds_cells * F::ESZ;
-    const Job J = jobs[job_offset + blockIdx.x];
-    const LeafProg P = progs[J.prog];
-    const uint32_t tid = threadIdx.x, nthr = blockDim.x;
-
-    copy_cells<F, true>(sm, x, J, J.nload, tid, nthr);
-    for (uint32_t t = tid; t < J.nload; t += nthr) stop[t] = x[cap * W + J.base + (uint64_t)t * J.stride];
-    __syncthreads();
-
-    const FermatOps<F> B;
-    const uint32_t wave = tid >> 6, nwaves = nthr >> 6;
-    const uint32_t g = B.lane / S;
-    for (uint32_t st = 0; st < P.step_count; ++st) {
-        const LeafStep LS = steps[P.step_begin + st];
-        for (uint32_t jb = wave * G; jb < LS.op_count; jb += nwaves * G) {
-            const uint32_t j = jb + g;
-            if (j < LS.op_count) {
-                const LeafOp o = ops[LS.op_begin + j];
-                const uint32_t code = o.w0 & 15u;
-                const uint32_t i0 = (o.w0 >> 4) & 16383u, i1 = (o.w0 >> 18) & 16383u;
-                const uint32_t e =
-                    (uint32_t)((((uint64_t)J.s << (o.w1 >> 24)) + (uint64_t)(o.w1 & 0xFFFFFFu)) & ord_mask);
-                uint32_t *x0 = sm + i0 * F::ESZ, *x1 = sm + i1 * F::ESZ;
-                uint32_t *t0 = stop + i0, *t1 = stop + i1;
-                switch (code) {
-                    case OP_T22:
-                        if constexpr (set_has<V>(OP_T22)) B.t22(x0, x1, t0, t1, e);
-                        break;
-                    case OP_T21:
-                        if constexpr (set_has<V>(OP_T21)) B.t21(x0, x1, t0, t1, e);
-                        break;
-                    case OP_T12:
-                        if constexpr (set_has<V>(OP_T12)) B.add2(x0, x1, t0, t1);
-                        break;
-                    case OP_I2:
-                        if constexpr (set_has<V>(OP_I2)) B.i2(x0, x1, t0, t1, (0u - e) & ord_mask);
-                        break;
-                    case OP_I1F1Z2:
-                        if constexpr (set_has<V>(OP_I1F1Z2)) B.i1f1(x0, x1, t0, t1, e, true);
-                        break;
-                    case OP_I1F1Z1:
-                        if constexpr (set_has<V>(OP_I1F1Z1)) B.i1f1(x0, x1, t0, t1, e, false);
-                        break;
-                    case OP_I1F0Z2:
-                        if constexpr (set_has<V>(OP_I1F0Z2)) B.dbl_sub(x0, x1, t0, t1);
-                        break;
-                    case OP_I1F0Z1:
-                        if constexpr (set_has<V>(OP_I1F0Z1)) B.dbl_sub(x0, nullptr, t0, nullptr);
-                        break;
-                    case OP_I0Z2:
-                        if constexpr (set_has<V>(OP_I0Z2)) {
-                            B.add2(x0, x1, t0, t1);
-                            B.scale(x0, t0, ord_mask);  // 2^(2N-1) = 1/2
-                        }
-                        break;
-                    case OP_I0Z1:
-                        if constexpr (set_has<V>(OP_I0Z1)) B.scale(x0, t0, ord_mask);
-                        break;
-                    default: break;
-                }
-            }
-        }
-        __syncthreads();
-    }
-
-    copy_cells<F, false>(sm, x, J, J.nstore, tid, nthr);
-    for (uint32_t t = tid; t < J.nstore; t += nthr) x[cap * W + J.base + (uint64_t)t * J.stride] = stop[t];
-}
-
-template <int S, int C, int V>
-__global__ void __launch_bounds__(512) fermat_leaf_kernel(const Job *__restrict__ jobs,
-                                                           const LeafProg *__restrict__ progs,
-                                                           const LeafStep *__restrict__ steps,
-                                                           const LeafOp *__restrict__ ops, uint32_t *__restrict__ x,
-                                                           uint64_t cap, uint32_t ord_mask, uint32_t lds_cells,
-                                                           uint32_t job_offset) {
-    leaf_body<S, C, V>(jobs, progs, steps, ops, x, cap, ord_mask, lds_cells, job_offset);
-}
 
 // ---------------------------------------------------------------------------
 // pointwise products  c = a b 2^scale_e  in Z/(2^N+1)
@@ -210,7 +36,7 @@ constexpr uint32_t pw_threads(int W) {
 
 // c = a b 2^scale_e for one product; a, b, c are W-limb cells (c may alias a or b),
 // ta, tb their top words, tc where c's top goes.  Called by a whole workgroup.
-template <int S, int C>
+template <int S, int C, bool TR>
 __device__ __forceinline__ void pointwise_body(const uint32_t *a, uint32_t ta, const uint32_t *b, uint32_t tb,
                                                uint32_t *c, uint32_t *tc, uint32_t scale_e) {
     using F = FChunk<S, C>;
@@ -223,8 +49,9 @@ __device__ __forceinline__ void pointwise_body(const uint32_t *a, uint32_t ta, c
     const uint32_t tid = threadIdx.x, nthr = blockDim.x;
 
     for (uint32_t q = tid; q < (uint32_t)W; q += nthr) {
-        A[q] = a[q];
-        Bv[q] = b[q];
+        const uint32_t g = TR ? F::addr(q) : q;  // global position of limb q
+        A[q] = a[g];
+        Bv[q] = b[g];
     }
     __syncthreads();
 
@@ -353,43 +180,56 @@ __device__ __forceinline__ void pointwise_body(const uint32_t *a, uint32_t ta, c
         }
     }
     __syncthreads();
-    for (uint32_t q = tid; q < (uint32_t)W; q += nthr) c[q] = Y[F::addr(q)];
+    for (uint32_t q = tid; q < (uint32_t)W; q += nthr) c[q] = Y[TR ? q : F::addr(q)];
     if (tid == 0) *tc = topY;
 }
 
-template <int S, int C>
+template <int S, int C, bool TR>
 __global__ void __launch_bounds__(256) fermat_pointwise_kernel(const uint32_t *__restrict__ a,
                                                                const uint32_t *__restrict__ b, uint32_t *c,
                                                                uint64_t cap, uint32_t scale_e, uint32_t base) {
     constexpr int W = S * C;
     const uint64_t i = (uint64_t)base + blockIdx.x;
-    pointwise_body<S, C>(a + i * W, a[cap * W + i], b + i * W, b[cap * W + i], c + i * W, c + cap * W + i, scale_e);
+    pointwise_body<S, C, TR>(a + i * W, a[cap * W + i], b + i * W, b[cap * W + i], c + i * W, c + cap * W + i,
+                             scale_e);
 }
 
 // Pointwise products over a list: item i multiplies cells it.x and it.y of the
 // cell array x (capacity cap) into cell it.x, with its own scale 2^it.z.
-template <int S, int C>
+template <int S, int C, bool TR>
 __global__ void __launch_bounds__(256) fermat_pointwise_items_kernel(uint32_t *x, uint64_t cap,
                                                                      const uint4 *__restrict__ items) {
     constexpr int W = S * C;
     const uint4 it = items[blockIdx.x];
     uint32_t *ca = x + (uint64_t)it.x * W, *cb = x + (uint64_t)it.y * W;
-    pointwise_body<S, C>(ca, x[cap * W + it.x], cb, x[cap * W + it.y], ca, x + cap * W + it.x, it.z);
+    pointwise_body<S, C, TR>(ca, x[cap * W + it.x], cb, x[cap * W + it.y], ca, x + cap * W + it.x, it.z);
 }
 
 // Pack: cell e of an operand holds coefficients e*k .. e*k+k-1, coefficient
 // e*k+j in limbs [j*ws, j*ws + climbs) (slot j), zeros elsewhere (Sect. 5.1 with
 // k = 1; k > 1 bundles k coefficients per ring element).  One descriptor per
 // operand, blockIdx.y selects it.
+// Position of limb k of a W-limb cell in the transposed layout (W = 64 C >= 128),
+// and its inverse; identity for W <= 64.
+__device__ __forceinline__ uint32_t tpos(uint32_t k, uint32_t W) {
+    const uint32_t C = W >> 6;
+    return C > 1 ? (k & (C - 1)) * 64u + k / C : k;
+}
+__device__ __forceinline__ uint32_t tlimb(uint32_t p, uint32_t W) {
+    const uint32_t C = W >> 6;
+    return C > 1 ? (p & 63u) * C + (p >> 6) : p;
+}
+
 __global__ void fermat_pack_kernel(const PackDesc *__restrict__ descs, PackDesc inl, uint32_t *__restrict__ x,
-                                   uint64_t cap, uint32_t W) {
+                                   uint64_t cap, uint32_t W, uint32_t tr) {
     const PackDesc d = descs ? descs[blockIdx.y] : inl;
     const uint64_t total = d.z * (uint64_t)W;
     for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < total;
          q += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t e = q / W;
         const uint32_t p = (uint32_t)(q % W);
-        const uint32_t j = p / d.ws, off = p % d.ws;
+        const uint32_t k = tr ? tlimb(p, W) : p;  // limb held at position p
+        const uint32_t j = k / d.ws, off = k % d.ws;
         const uint64_t c = e * d.k + j;
         x[(d.cell0 + e) * W + p] = (j < d.k && off < d.climbs && c < d.len) ? d.coef[c * d.climbs + off] : 0u;
         if (p == 0) x[cap * W + d.cell0 + e] = 0u;
@@ -398,7 +238,7 @@ __global__ void fermat_pack_kernel(const PackDesc *__restrict__ descs, PackDesc 
 
 // Unpack with k = 1: coefficient t is the low limbs of cell t.
 __global__ void fermat_unpack1_kernel(const UnpackDesc *__restrict__ descs, UnpackDesc inl,
-                                      const uint32_t *__restrict__ x, uint64_t cap, uint32_t W) {
+                                      const uint32_t *__restrict__ x, uint64_t cap, uint32_t W, uint32_t tr) {
     const UnpackDesc d = descs ? descs[blockIdx.y] : inl;
     const uint64_t total = d.len_out * (uint64_t)d.olimbs;
     for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < total;
@@ -406,75 +246,34 @@ __global__ void fermat_unpack1_kernel(const UnpackDesc *__restrict__ descs, Unpa
         const uint64_t t = q / d.olimbs;
         const uint32_t i = (uint32_t)(q % d.olimbs);
         const uint64_t cell = d.cell0 + t;
-        d.out[q] = i < W ? x[cell * W + i] : (i == W ? x[cap * W + cell] : 0u);
+        d.out[q] = i < W ? x[cell * W + (tr ? tpos(i, W) : i)] : (i == W ? x[cap * W + cell] : 0u);
     }
 }
 
 // Unpack with k > 1: the product cell m holds slots 0..2k-2 of width ws limbs;
 // coefficient t = m k + j is slot j of cell m plus slot j + k of cell m - 1.
 __global__ void fermat_unpackk_kernel(const UnpackDesc *__restrict__ descs, UnpackDesc inl,
-                                      const uint32_t *__restrict__ x, uint32_t W) {
+                                      const uint32_t *__restrict__ x, uint32_t W, uint32_t tr) {
     const UnpackDesc d = descs ? descs[blockIdx.y] : inl;
     for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < d.len_out;
          t += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t m = t / d.k;
         const uint32_t j = (uint32_t)(t % d.k);
-        const uint32_t *s0 = (m < d.ncells) ? x + (d.cell0 + m) * W + (uint64_t)j * d.ws : nullptr;
-        const uint32_t *s1 = (m >= 1 && j + 1 < d.k && m - 1 < d.ncells)
-                                 ? x + (d.cell0 + m - 1) * W + (uint64_t)(j + d.k) * d.ws
-                                 : nullptr;
+        // slot j of cell m and slot j + k of cell m - 1 (limbs j ws + i, (j + k) ws + i)
+        const uint32_t *s0 = (m < d.ncells) ? x + (d.cell0 + m) * W : nullptr;
+        const uint32_t *s1 = (m >= 1 && j + 1 < d.k && m - 1 < d.ncells) ? x + (d.cell0 + m - 1) * W : nullptr;
+        const uint32_t k0 = j * d.ws, k1 = (j + d.k) * d.ws;
         uint32_t *o = d.out + t * d.olimbs;
         uint64_t c = 0;
         for (uint32_t i = 0; i < d.olimbs; ++i) {
             if (i < d.ws) {
-                c += (s0 ? s0[i] : 0u);
-                c += (s1 ? s1[i] : 0u);
+                c += (s0 ? s0[tr ? tpos(k0 + i, W) : k0 + i] : 0u);
+                c += (s1 ? s1[tr ? tpos(k1 + i, W) : k1 + i] : 0u);
             }
             o[i] = (uint32_t)c;
             c >>= 32;
         }
     }
-}
-
-template <int S, int C, int V>
-hipError_t leaf_launch_set(uint32_t nwaves, uint32_t njobs, uint32_t lds_cells, const Job *jobs, uint32_t job_offset,
-                           const LeafProg *progs, const LeafStep *steps, const LeafOp *ops, uint32_t *x, uint64_t cap,
-                           uint32_t ord_mask, hipStream_t st) {
-    const size_t lds = (size_t)lds_cells * (FChunk<S, C>::ESZ + 1) * 4;
-    if (lds > kLdsBudget - kLeafStaticLds) return hipErrorInvalidValue;
-    auto kern = &fermat_leaf_kernel<S, C, V>;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)(kLdsBudget - kLeafStaticLds));
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    // a launch covers at most 2^32 - 1 work-items per grid dimension
-    const uint32_t per = kMaxGridX / (64 * nwaves);
-    for (uint32_t j0 = 0; j0 < njobs; j0 += per) {
-        const uint32_t nb = njobs - j0 < per ? njobs - j0 : per;
-        hipLaunchKernelGGL(kern, dim3(nb), dim3(64 * nwaves), lds, st, jobs, progs, steps, ops, x, cap, ord_mask,
-                           lds_cells, job_offset + j0);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-}
-
-template <int S, int C>
-hipError_t leaf_launch(uint32_t nwaves, uint32_t njobs, uint32_t lds_cells, const Job *jobs, uint32_t job_offset,
-                       const LeafProg *progs, const LeafStep *steps, const LeafOp *ops, uint32_t *x, uint64_t cap,
-                       uint32_t ord_mask, uint32_t opmask, hipStream_t st) {
-    if ((opmask & ~kTftOps) == 0u)
-        return leaf_launch_set<S, C, SET_TFT>(nwaves, njobs, lds_cells, jobs, job_offset, progs, steps, ops, x, cap,
-                                              ord_mask, st);
-    if ((opmask & ~kItftOps) == 0u)
-        return leaf_launch_set<S, C, SET_ITFT>(nwaves, njobs, lds_cells, jobs, job_offset, progs, steps, ops, x, cap,
-                                               ord_mask, st);
-    return leaf_launch_set<S, C, SET_ALL>(nwaves, njobs, lds_cells, jobs, job_offset, progs, steps, ops, x, cap,
-                                          ord_mask, st);
 }
 
 template <class KernelT>
@@ -486,19 +285,19 @@ hipError_t pointwise_attr(KernelT *kern, size_t lds, bool &done) {
     return e;
 }
 
-template <int S, int C>
+template <int S, int C, bool TR>
 hipError_t pointwise_launch(uint64_t n, const uint32_t *a, const uint32_t *b, uint32_t *c, uint64_t cap,
                             uint32_t scale_e, hipStream_t st) {
     constexpr int W = S * C;
     const size_t lds = (size_t)(8 * W + FChunk<S, C>::ESZ + 1) * 4;
     if (lds > kLdsBudget) return hipErrorInvalidValue;
     static bool attr = false;
-    hipError_t e = pointwise_attr(&fermat_pointwise_kernel<S, C>, lds, attr);
+    hipError_t e = pointwise_attr(&fermat_pointwise_kernel<S, C, TR>, lds, attr);
     if (e != hipSuccess) return e;
     const uint64_t per = kMaxGridX / pw_threads(W);
     for (uint64_t i0 = 0; i0 < n; i0 += per) {
         const uint64_t nb = n - i0 < per ? n - i0 : per;
-        hipLaunchKernelGGL((fermat_pointwise_kernel<S, C>), dim3((uint32_t)nb), dim3(pw_threads(W)), lds, st, a, b,
+        hipLaunchKernelGGL((fermat_pointwise_kernel<S, C, TR>), dim3((uint32_t)nb), dim3(pw_threads(W)), lds, st, a, b,
                            c, cap, scale_e, (uint32_t)i0);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -506,18 +305,18 @@ hipError_t pointwise_launch(uint64_t n, const uint32_t *a, const uint32_t *b, ui
     return hipSuccess;
 }
 
-template <int S, int C>
+template <int S, int C, bool TR>
 hipError_t pointwise_items_launch(uint64_t nitems, uint32_t *x, uint64_t cap, const uint4 *items, hipStream_t st) {
     constexpr int W = S * C;
     const size_t lds = (size_t)(8 * W + FChunk<S, C>::ESZ + 1) * 4;
     if (lds > kLdsBudget) return hipErrorInvalidValue;
     static bool attr = false;
-    hipError_t e = pointwise_attr(&fermat_pointwise_items_kernel<S, C>, lds, attr);
+    hipError_t e = pointwise_attr(&fermat_pointwise_items_kernel<S, C, TR>, lds, attr);
     if (e != hipSuccess) return e;
     const uint64_t per = kMaxGridX / pw_threads(W);
     for (uint64_t i0 = 0; i0 < nitems; i0 += per) {
         const uint64_t nb = nitems - i0 < per ? nitems - i0 : per;
-        hipLaunchKernelGGL((fermat_pointwise_items_kernel<S, C>), dim3((uint32_t)nb), dim3(pw_threads(W)), lds, st,
+        hipLaunchKernelGGL((fermat_pointwise_items_kernel<S, C, TR>), dim3((uint32_t)nb), dim3(pw_threads(W)), lds, st,
                            x, cap, items + i0);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -529,72 +328,72 @@ hipError_t pointwise_items_launch(uint64_t nitems, uint32_t *x, uint64_t cap, co
 
 uint32_t lds_budget_bytes() { return kLdsBudget - kLeafStaticLds; }
 
-uint32_t fermat_lds_cell_bytes(uint32_t W) {
-    const uint32_t S = W < 64 ? W : 64, C = W / S;
-    const uint32_t CP = C > 1 ? C + 1 : 1;
-    return 4u * (S * CP + 1u);
-}
-
-#define TFT_FERMAT_DISPATCH(W, FN, ...)                      \
-    switch (W) {                                             \
-        case 1: return FN<1, 1>(__VA_ARGS__);                \
-        case 2: return FN<2, 1>(__VA_ARGS__);                \
-        case 4: return FN<4, 1>(__VA_ARGS__);                \
-        case 8: return FN<8, 1>(__VA_ARGS__);                \
-        case 16: return FN<16, 1>(__VA_ARGS__);              \
-        case 32: return FN<32, 1>(__VA_ARGS__);              \
-        case 64: return FN<64, 1>(__VA_ARGS__);              \
-        case 128: return FN<64, 2>(__VA_ARGS__);             \
-        case 256: return FN<64, 4>(__VA_ARGS__);             \
-        case 512: return FN<64, 8>(__VA_ARGS__);             \
-        case 1024: return FN<64, 16>(__VA_ARGS__);           \
-        case 2048: return FN<64, 32>(__VA_ARGS__);           \
-        case 4096: return FN<64, 64>(__VA_ARGS__);           \
-        default: return hipErrorInvalidValue;                \
-    }
-
 hipError_t launch_fermat_leaf(uint32_t W, uint32_t nwaves, uint32_t njobs, uint32_t lds_cells, const Job *jobs,
                               uint32_t job_offset, const LeafProg *progs, const LeafStep *steps, const LeafOp *ops,
-                              uint32_t *x, uint64_t cap, uint32_t ord_mask, uint32_t opmask, hipStream_t st) {
-    if (njobs == 0) return hipSuccess;
-    TFT_FERMAT_DISPATCH(W, leaf_launch, nwaves, njobs, lds_cells, jobs, job_offset, progs, steps, ops, x, cap,
-                        ord_mask, opmask, st)
+                              uint32_t *x, uint64_t cap, uint32_t ord_mask, uint32_t opmask, bool transposed,
+                              hipStream_t st) {
+    return transposed ? launch_fermat_leaf_trans(W, nwaves, njobs, lds_cells, jobs, job_offset, progs, steps, ops, x,
+                                                 cap, ord_mask, opmask, st)
+                      : launch_fermat_leaf_plain(W, nwaves, njobs, lds_cells, jobs, job_offset, progs, steps, ops, x,
+                                                 cap, ord_mask, opmask, st);
 }
 
+uint32_t fermat_lds_cell_bytes(uint32_t W) { return 4u * (W + 1u); }
+
+template <bool TR>
+struct PwLaunch {
+    template <int S, int C>
+    static hipError_t run(uint64_t n, const uint32_t *a, const uint32_t *b, uint32_t *c, uint64_t cap,
+                          uint32_t scale_e, hipStream_t st) {
+        return pointwise_launch<S, C, TR>(n, a, b, c, cap, scale_e, st);
+    }
+    template <int S, int C>
+    static hipError_t items(uint64_t nitems, uint32_t *x, uint64_t cap, const uint4 *it, hipStream_t st) {
+        return pointwise_items_launch<S, C, TR>(nitems, x, cap, it, st);
+    }
+};
+
 hipError_t launch_fermat_pointwise(uint32_t W, uint64_t n, const uint32_t *a, const uint32_t *b, uint32_t *c,
-                                   uint64_t cap, uint32_t scale_e, hipStream_t st) {
+                                   uint64_t cap, uint32_t scale_e, bool transposed, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    TFT_FERMAT_DISPATCH(W, pointwise_launch, n, a, b, c, cap, scale_e, st)
+    if (transposed) {
+        TFT_FERMAT_DISPATCH(W, PwLaunch<true>::run, n, a, b, c, cap, scale_e, st)
+    }
+    TFT_FERMAT_DISPATCH(W, PwLaunch<false>::run, n, a, b, c, cap, scale_e, st)
 }
 
 hipError_t launch_fermat_pointwise_items(uint32_t W, uint64_t nitems, uint32_t *x, uint64_t cap, const uint4 *items,
-                                         hipStream_t st) {
+                                         bool transposed, hipStream_t st) {
     if (nitems == 0) return hipSuccess;
-    TFT_FERMAT_DISPATCH(W, pointwise_items_launch, nitems, x, cap, items, st)
+    if (!transposed) return hipErrorInvalidValue;  // products keep their cell arrays transposed
+    TFT_FERMAT_DISPATCH(W, PwLaunch<true>::items, nitems, x, cap, items, st)
 }
 
 hipError_t launch_fermat_pack(uint32_t W, const PackDesc *descs, uint32_t ndesc, const PackDesc &inl, uint64_t max_z,
-                              uint32_t *x, uint64_t cap, hipStream_t st) {
+                              uint32_t *x, uint64_t cap, bool transposed, hipStream_t st) {
     if (ndesc == 0 || max_z == 0) return hipSuccess;
     uint64_t blocks = (max_z * W + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(fermat_pack_kernel, dim3((uint32_t)blocks, ndesc), dim3(256), 0, st, descs, inl, x, cap, W);
+    hipLaunchKernelGGL(fermat_pack_kernel, dim3((uint32_t)blocks, ndesc), dim3(256), 0, st, descs, inl, x, cap, W,
+                       transposed ? 1u : 0u);
     return hipGetLastError();
 }
 
 hipError_t launch_fermat_unpack(uint32_t W, const UnpackDesc *descs, uint32_t ndesc, const UnpackDesc &inl,
                                 uint64_t max_len, uint32_t max_olimbs, bool bundled, const uint32_t *x, uint64_t cap,
-                                hipStream_t st) {
+                                bool transposed, hipStream_t st) {
     if (ndesc == 0 || max_len == 0) return hipSuccess;
+    const uint32_t tr = transposed ? 1u : 0u;
     if (!bundled) {
         uint64_t blocks = (max_len * max_olimbs + 255) / 256;
         if (blocks > 4096) blocks = 4096;
         hipLaunchKernelGGL(fermat_unpack1_kernel, dim3((uint32_t)blocks, ndesc), dim3(256), 0, st, descs, inl, x, cap,
-                           W);
+                           W, tr);
     } else {
         uint64_t blocks = (max_len + 255) / 256;
         if (blocks > 4096) blocks = 4096;
-        hipLaunchKernelGGL(fermat_unpackk_kernel, dim3((uint32_t)blocks, ndesc), dim3(256), 0, st, descs, inl, x, W);
+        hipLaunchKernelGGL(fermat_unpackk_kernel, dim3((uint32_t)blocks, ndesc), dim3(256), 0, st, descs, inl, x, W,
+                           tr);
     }
     return hipGetLastError();
 }

@@ -16,11 +16,15 @@
 // Multiplication by 2^e (every twiddle; Sect. 6 keeps zeta as its exponent)
 // is a rotation by t = e mod N bits with the bits that pass 2^N negated
 // (2^N = -1), and a global sign when e >= N.  It reads the element from LDS
-// at rotated addresses; LDS stores chunks at an odd stride (C+1 for C > 1) so
-// that 64 lanes reading one limb of their chunks hit 64 distinct banks.
+// at rotated addresses.  In LDS an element is stored transposed: limb k at
+// position (k mod C) S + k / C, so that the S lanes reading limb j of their
+// chunks read S consecutive words (distinct banks) at a fixed offset j S.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
+#include <utility>
 
 namespace tft {
 
@@ -55,8 +59,7 @@ struct FChunk {
     static constexpr int C = C_;
     static constexpr int W = S * C;
     static constexpr uint32_t N = 32u * W;
-    static constexpr int CP = C > 1 ? C + 1 : 1;  // LDS dwords per chunk
-    static constexpr int ESZ = S * CP;             // LDS dwords per element
+    static constexpr int ESZ = W;  // LDS dwords per element
     static constexpr uint64_t FIRST = seg_mask(S, 0);
     static constexpr uint64_t LAST = seg_mask(S, S - 1);
     static_assert(S == 64 || C == 1, "segments narrower than a wave hold one limb per lane");
@@ -73,7 +76,7 @@ struct FChunk {
     }
 
     // LDS position of limb k of an element
-    __device__ static __forceinline__ uint32_t addr(uint32_t k) { return (k / C) * CP + (k % C); }
+    __device__ static __forceinline__ uint32_t addr(uint32_t k) { return (k % C) * S + k / C; }
 
     __device__ __forceinline__ uint32_t seg_bit(uint64_t m, int off) const {
         return (uint32_t)((m >> (g0 + off)) & 1ull);
@@ -81,11 +84,11 @@ struct FChunk {
 
     __device__ __forceinline__ void ld(const uint32_t *x, uint32_t (&v)[C]) const {
 #pragma unroll
-        for (int j = 0; j < C; ++j) v[j] = x[l * CP + j];
+        for (int j = 0; j < C; ++j) v[j] = x[j * S + l];
     }
     __device__ __forceinline__ void st(uint32_t *x, const uint32_t (&v)[C]) const {
 #pragma unroll
-        for (int j = 0; j < C; ++j) x[l * CP + j] = v[j];
+        for (int j = 0; j < C; ++j) x[j * S + l] = v[j];
     }
 
     // Carry (borrow) cy out of each lane's chunk enters the next lane; repeat
@@ -218,6 +221,46 @@ struct Rot {
     }
 };
 
+// Per-lane masks of a rotation: limb j of the lane's chunk takes its bits
+// below position t (the wrapped part) from mask low(j) = all ones for j < jq,
+// the partial mask pm for j = jq, zero above, with jq = q - l*C.  Built once
+// per operation as two bit sets, then one sign-extending bit extract and one
+// and-or per limb (no compare/select through lane masks).
+template <int C>
+struct RotMask {
+    using B = typename std::conditional<(C > 32), uint64_t, uint32_t>::type;
+    B lt, eq;  // bit j: j < jq; j == jq
+    uint32_t pm;
+
+    __device__ __forceinline__ RotMask(int jq, uint32_t pm_) : pm(pm_) {
+        constexpr int NB = C > 32 ? 64 : 32;
+        lt = jq >= C ? ~B(0) : (jq <= 0 ? B(0) : ((B(1) << jq) - B(1)));
+        eq = (jq >= 0 && jq < C) ? (B(1) << jq) : B(0);
+        (void)NB;
+    }
+    template <int J>
+    __device__ __forceinline__ static uint32_t ext(B v) {  // 0 or all ones from bit J
+        if constexpr (C > 32) {
+            const uint32_t w = J < 32 ? (uint32_t)v : (uint32_t)(v >> 32);
+            return (uint32_t)(((int32_t)(w << (31 - (J & 31)))) >> 31);
+        } else {
+            return (uint32_t)(((int32_t)(v << (31 - J))) >> 31);
+        }
+    }
+    template <int J>
+    __device__ __forceinline__ uint32_t low() const {
+        return ext<J>(lt) | (ext<J>(eq) & pm);
+    }
+};
+
+template <int J, int N, class Fn>
+__device__ __forceinline__ void static_for(Fn &&f) {
+    if constexpr (J < N) {
+        f(std::integral_constant<int, J>{});
+        static_for<J + 1, N>(f);
+    }
+}
+
 // The base cases of Alg. 1 and Alg. 2 on canonical cells in LDS.
 template <class F>
 struct FermatOps : F {
@@ -227,20 +270,37 @@ struct FermatOps : F {
     // v = sgn * (Lo - Hi) for x rotated left by t bits within N bits: Lo are the
     // bits that stay below 2^N, Hi the bits that wrapped (they count negatively).
     // Returns the borrow out of the element.
+    // Limbs l C - qp + i (mod W), i = 0..C, of the element at x (the lane's
+    // chunk shifted down by qp limbs).  For one element per wave they lie in
+    // LDS rows row0 + i (column col0) and row0 + i - C (column col0 + 1), with
+    // row0 the same for every lane: one select between two bases per limb.
+    __device__ __forceinline__ void rot_words(const uint32_t *x, uint32_t qp, uint32_t (&src)[C + 1]) const {
+        if constexpr (F::S == 64 && C > 1) {
+            const uint32_t row0 = __builtin_amdgcn_readfirstlane((0u - qp) & (uint32_t)(C - 1));
+            const uint32_t col0 = ((this->l * C - qp) & (uint32_t)(W - 1)) / C, col1 = (col0 + 1u) & 63u;
+            const uint32_t oA = row0 * 64u + col0;
+            const uint32_t oB = row0 * 64u + col1 - 64u * C;  // used only where oB + 64 i >= 0
+#pragma unroll
+            for (int i = 0; i <= C; ++i) src[i] = x[((uint32_t)i + row0 < (uint32_t)C ? oA : oB) + 64u * i];
+        } else {
+#pragma unroll
+            for (int i = 0; i <= C; ++i) src[i] = x[F::addr((this->l * C - qp + (uint32_t)i) & (uint32_t)(W - 1))];
+        }
+    }
+
     template <bool NEG>
     __device__ __forceinline__ uint32_t rot_sub_impl(const uint32_t *x, const Rot<F> &rt, uint32_t (&v)[C]) const {
         uint32_t src[C + 1];
-#pragma unroll
-        for (int i = 0; i <= C; ++i) src[i] = x[F::addr((this->l * C - rt.qp + (uint32_t)i) & (uint32_t)(W - 1))];
-        const int jq = (int)rt.q - (int)(this->l * C);
+        rot_words(x, rt.qp, src);
+        const RotMask<C> mk((int)rt.q - (int)(this->l * C), rt.pm);
         uint32_t b = 0;
-#pragma unroll
-        for (int j = 0; j < C; ++j) {
+        static_for<0, C>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
             const uint32_t r = __builtin_amdgcn_alignbit(src[j + 1], src[j], rt.c);
-            const uint32_t low = (j < jq) ? 0xFFFFFFFFu : ((j == jq) ? rt.pm : 0u);
+            const uint32_t low = mk.template low<j>();
             const uint32_t hp = r & low, lp = r & ~low;
             v[j] = NEG ? subb(hp, lp, b) : subb(lp, hp, b);
-        }
+        });
         return this->settle(v, b, true);
     }
     __device__ __forceinline__ uint32_t rot_sub(const uint32_t *x, const Rot<F> &rt, uint32_t (&v)[C]) const {
@@ -271,22 +331,18 @@ struct FermatOps : F {
         uint32_t bd = 0;
         {
             uint32_t s0[C + 1], s1[C + 1];
-#pragma unroll
-            for (int i = 0; i <= C; ++i) {
-                const uint32_t ad = F::addr((this->l * C - rt.qp + (uint32_t)i) & (uint32_t)(W - 1));
-                s0[i] = x0[ad];
-                s1[i] = x1[ad];
-            }
-            const int jq = (int)rt.q - (int)(this->l * C);
-#pragma unroll
-            for (int j = 0; j < C; ++j) {
+            rot_words(x0, rt.qp, s0);
+            rot_words(x1, rt.qp, s1);
+            const RotMask<C> mk((int)rt.q - (int)(this->l * C), rt.pm);
+            static_for<0, C>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
                 const uint32_t r0 = __builtin_amdgcn_alignbit(s0[j + 1], s0[j], rt.c);
                 const uint32_t r1 = __builtin_amdgcn_alignbit(s1[j + 1], s1[j], rt.c);
-                const uint32_t low = (j < jq) ? 0xFFFFFFFFu : ((j == jq) ? rt.pm : 0u);
+                const uint32_t low = mk.template low<j>();
                 const uint32_t A = (r1 & low) | (r0 & ~low);
                 const uint32_t B = (r0 & low) | (r1 & ~low);
                 d[j] = NEG ? subb(B, A, bd) : subb(A, B, bd);
-            }
+            });
         }
         const uint32_t bv = this->settle(d, bd, true);
         __builtin_amdgcn_sched_barrier(0);  // keep the sum's loads after the difference (register pressure)

@@ -7,30 +7,44 @@
 
 namespace tft {
 
+// Cell layouts in global memory: plain (limb k of a cell at offset k, the ABI
+// layout) or transposed (limb k at (k mod C) 64 + k / C for W = 64 C >= 128, the
+// order a leaf keeps in LDS; used for the cell arrays inside products).  For
+// W <= 64 both are the same.
+
 // Leaf workgroups for one pass of a Fermat-ring transform.
 // opmask: BaseOp bits the pass's programs use; selects a kernel compiled for that set of base cases.
 hipError_t launch_fermat_leaf(uint32_t W, uint32_t nwaves, uint32_t njobs, uint32_t lds_cells, const Job *jobs,
                               uint32_t job_offset, const LeafProg *progs, const LeafStep *steps, const LeafOp *ops,
-                              uint32_t *x, uint64_t cap, uint32_t ord_mask, uint32_t opmask, hipStream_t st);
+                              uint32_t *x, uint64_t cap, uint32_t ord_mask, uint32_t opmask, bool transposed,
+                              hipStream_t st);
+hipError_t launch_fermat_leaf_plain(uint32_t W, uint32_t nwaves, uint32_t njobs, uint32_t lds_cells, const Job *jobs,
+                                    uint32_t job_offset, const LeafProg *progs, const LeafStep *steps,
+                                    const LeafOp *ops, uint32_t *x, uint64_t cap, uint32_t ord_mask, uint32_t opmask,
+                                    hipStream_t st);
+hipError_t launch_fermat_leaf_trans(uint32_t W, uint32_t nwaves, uint32_t njobs, uint32_t lds_cells, const Job *jobs,
+                                    uint32_t job_offset, const LeafProg *progs, const LeafStep *steps,
+                                    const LeafOp *ops, uint32_t *x, uint64_t cap, uint32_t ord_mask, uint32_t opmask,
+                                    hipStream_t st);
 
 // c_i = a_i b_i 2^scale_e (scale_e = -scale_log2 mod 2N) for i < n, cell arrays of capacity cap.
 hipError_t launch_fermat_pointwise(uint32_t W, uint64_t n, const uint32_t *a, const uint32_t *b, uint32_t *c,
-                                   uint64_t cap, uint32_t scale_e, hipStream_t st);
+                                   uint64_t cap, uint32_t scale_e, bool transposed, hipStream_t st);
 
 // Pointwise products over an item list on one cell array (see fermat_pointwise_items_kernel).
 hipError_t launch_fermat_pointwise_items(uint32_t W, uint64_t nitems, uint32_t *x, uint64_t cap, const uint4 *items,
-                                         hipStream_t st);
+                                         bool transposed, hipStream_t st);
 
 // Coefficients -> cells, one descriptor per operand: a device array of ndesc
 // descriptors, or (descs == nullptr, ndesc == 1) the descriptor inl passed by value.
 hipError_t launch_fermat_pack(uint32_t W, const PackDesc *descs, uint32_t ndesc, const PackDesc &inl, uint64_t max_z,
-                              uint32_t *x, uint64_t cap, hipStream_t st);
+                              uint32_t *x, uint64_t cap, bool transposed, hipStream_t st);
 
 // Cells -> coefficients, one descriptor per product (device array or inl as above);
 // bundled = the descriptors have k > 1 (all of one launch alike).
 hipError_t launch_fermat_unpack(uint32_t W, const UnpackDesc *descs, uint32_t ndesc, const UnpackDesc &inl,
                                 uint64_t max_len, uint32_t max_olimbs, bool bundled, const uint32_t *x, uint64_t cap,
-                                hipStream_t st);
+                                bool transposed, hipStream_t st);
 
 // Largest LDS bytes one workgroup may use.
 uint32_t lds_budget_bytes();
@@ -38,7 +52,7 @@ uint32_t lds_budget_bytes();
 // Records a failed HIP call for tft_last_error; returns TFT_E_DEVICE.
 int device_error(hipError_t e, const char *where);
 
-// LDS bytes of one Fermat cell inside a leaf workgroup (padded chunk layout plus top word).
+// LDS bytes of one Fermat cell inside a leaf workgroup (limbs plus top word).
 uint32_t fermat_lds_cell_bytes(uint32_t W);
 
 }  // namespace tft
