@@ -76,6 +76,21 @@ uint32_t max_leaf_log2(const tft_ring *r) {
     return std::min<uint32_t>(lg, 11);
 }
 
+// log2 of twice the compute units of the current device (cached per device)
+uint32_t fill_log2() {
+    static uint32_t cache[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 9;
+    if (!cache[dev]) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+        uint32_t lg = 0;
+        while ((1u << lg) < 2u * (uint32_t)cus) lg++;
+        cache[dev] = lg;
+    }
+    return cache[dev];
+}
+
 thread_local char g_last_error[256] = "";
 
 // Records the HIP error of a failed call (readable through tft_last_error) and
@@ -412,7 +427,15 @@ static int ss_run(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uin
     tft_ring ring{TFT_RING_FERMAT, sh.N, 0, 0, 0};
     uint32_t *A = static_cast<uint32_t *>(ws);
     uint32_t *B = A + sh.L * (sh.W + 1);
-    const tft_split *split = params ? &params->split : nullptr;
+    // One product on its own: unless the caller chose the leaf, cap it so that a
+    // pass still has about two leaf jobs per compute unit (larger leaves mean
+    // fewer passes, but a pass of fewer jobs than CUs leaves the GPU part idle).
+    tft_split sp = params ? params->split : tft_split{0, 0};
+    if (!sp.leaf_log2) {
+        const uint32_t fit = max_leaf_log2(&ring), fill = fill_log2();
+        sp.leaf_log2 = (sh.l > fill + 3) ? std::min(fit, std::max<uint32_t>(3, sh.l - fill)) : fit;
+    }
+    const tft_split *split = &sp;
     tft_plan *pg = cached_plan(&ring, 0, sh.l, 0, sh.zg, sh.n, 0, split);
     tft_plan *ph = cached_plan(&ring, 0, sh.l, 0, sh.zh, sh.n, 0, split);
     tft_plan *pi = cached_plan(&ring, 1, sh.l, 0, sh.n, sh.n, 0, split);
