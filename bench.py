@@ -91,6 +91,35 @@ def cpu_baseline(g_limbs_arr, N, l, z, n, alg_bytes, budget_s=15.0):
                                                                                           total_s)}
 
 
+def _source_hash():
+    """Hash of the library sources (kernels, planner, ABI): identifies the kernel version profiled."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_0810_3203_amd", "csrc", "*"))) + [
+        os.path.join(ROOT, "include", "tft.h")]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(path=os.path.join(ROOT, "profiles", "ss_large_L2e17_pmc_traffic.md")):
+    """HBM bytes per leaf launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, if it was
+    taken with the current sources (else None: the counters describe another kernel)."""
+    import re
+    try:
+        with open(path) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    m = re.search(r"when measured: `([0-9a-f]+)` \(traffic_bytes_per_launch = (\d+)\)", text)
+    if not m or m.group(1) != _source_hash():
+        return None
+    return int(m.group(2))
+
+
 def _progress(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
@@ -313,7 +342,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": profiled_traffic(),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "alg_bytes_per_launch": int(alg_bytes / max(1, launches)),
             "kernel": "fermat_leaf_kernel<64,32> (%d launches per step)" % launches,
             "avg_launch_ms": round(leaf_ms / max(1, launches), 4),
         },
