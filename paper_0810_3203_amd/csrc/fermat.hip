@@ -17,22 +17,27 @@ namespace {
 // pointwise products  c = a b 2^scale_e  in Z/(2^N+1)
 //
 // One workgroup per product.  The negacyclic limb convolution
-//   d_k = sum_{i+j=k} a_i b_j - sum_{i+j=k+W} a_i b_j     (2^N = -1)
-// is accumulated per output column in 96-bit sums (P_k, N_k), each thread
-// owning 8 consecutive columns and sliding a register window over b.  The
-// column sums are then folded into four limb vectors PL + HP - NL - HN that
-// one wave adds with the carry-lookahead chains, followed by canonicalisation
-// and the multiplication by 2^scale_e.
+//   d_k = sum_{j<=k} b_j a_{k-j} - sum_{j>k} b_j a_{k-j+W}          (2^N = -1)
+// is computed without a sign test per product: with the doubled array
+// A2 = [a_0..a_{W-1}, ~a_0..~a_{W-1}] (~a = 2^32 - 1 - a) and the suffix sums
+// T_k = sum_{j>k} b_j,
+//   d_k = S_k + T_k - 2^32 T_k,   S_k = sum_{j<W} b_j A2[(k - j) mod 2W],
+// where S_k is a sum of unsigned products accumulated in 96 bits.  Each thread
+// owns NC consecutive columns and slides a register window over A2.  The
+// positive parts S_k + T_k and negative parts 2^32 T_k are then folded into
+// four limb vectors that one wave adds with the chunk chains, followed by
+// canonicalisation and the multiplication by 2^scale_e.
 // ---------------------------------------------------------------------------
 
-constexpr int PW_COLS = 8;
-
-// threads of a pointwise workgroup for W limbs: one per PW_COLS columns, 64..256
+// threads of a pointwise workgroup for W limbs (64..256) and columns per thread
 constexpr uint32_t pw_threads(int W) {
-    uint32_t t = (uint32_t)W / PW_COLS;
+    uint32_t t = (uint32_t)W / 8u;
     t = t < 64 ? 64 : (t > 256 ? 256 : t);
     return (t + 63) / 64 * 64;
 }
+constexpr int pw_cols(int W) { return W / (int)pw_threads(W) > 0 ? W / (int)pw_threads(W) : 1; }
+// LDS words of a pointwise workgroup: A2 (2W), B (W), six column-word arrays (6W)
+constexpr uint32_t pw_lds_words(int W) { return 9u * (uint32_t)W; }
 
 // c = a b 2^scale_e for one product; a, b, c are W-limb cells (c may alias a or b),
 // ta, tb their top words, tc where c's top goes.  Called by a whole workgroup.
@@ -41,62 +46,87 @@ __device__ __forceinline__ void pointwise_body(const uint32_t *a, uint32_t ta, c
                                                uint32_t *c, uint32_t *tc, uint32_t scale_e) {
     using F = FChunk<S, C>;
     constexpr int W = F::W;
+    constexpr int NC = pw_cols(W);
     extern __shared__ uint32_t sm[];
-    uint32_t *A = sm, *Bv = A + W;
+    uint32_t *A = sm, *Bv = A + 2 * W;
     uint32_t *P0 = Bv + W, *P1 = P0 + W, *P2 = P1 + W, *N0 = P2 + W, *N1 = N0 + W, *N2 = N1 + W;
-    uint32_t *Y = N2 + W;  // F::ESZ dwords, LDS layout of one element
+    uint32_t *Y = sm;  // F::ESZ dwords (LDS layout of one element) plus its top: reuses A2 at the end
     uint32_t &topY = Y[F::ESZ];
     const uint32_t tid = threadIdx.x, nthr = blockDim.x;
 
     for (uint32_t q = tid; q < (uint32_t)W; q += nthr) {
         const uint32_t g = TR ? F::addr(q) : q;  // global position of limb q
-        A[q] = a[g];
+        const uint32_t av = a[g];
+        A[q] = av;
+        A[q + W] = ~av;
         Bv[q] = b[g];
     }
     __syncthreads();
 
     const bool special = (ta | tb) != 0u;
     if (!special) {
-        // column sums, PW_COLS consecutive columns per thread
-        for (uint32_t k0 = tid * PW_COLS; k0 < (uint32_t)W; k0 += nthr * PW_COLS) {
-            constexpr int NC = (W < PW_COLS) ? W : PW_COLS;
-            uint64_t pl[NC], nl[NC];
-            uint32_t ph[NC], nh[NC], bw[NC];
+        // suffix sums T_k = sum_{j>k} b_j (64-bit) in P0 (low) / P1 (high): a doubling scan over W words
+        for (uint32_t q = tid; q < (uint32_t)W; q += nthr) {
+            P0[q] = q + 1 < (uint32_t)W ? Bv[q + 1] : 0u;
+            P1[q] = 0u;
+        }
+        __syncthreads();
+        constexpr int NQ = (W + (int)pw_threads(W) - 1) / (int)pw_threads(W);  // words per thread
+        for (uint32_t d = 1; d < (uint32_t)W; d <<= 1) {
+            uint64_t add[NQ];
+            uint32_t na = 0;
+            for (uint32_t q = tid; q < (uint32_t)W; q += nthr, ++na)
+                add[na] = q + d < (uint32_t)W ? ((uint64_t)P1[q + d] << 32 | P0[q + d]) : 0ull;
+            __syncthreads();
+            na = 0;
+            for (uint32_t q = tid; q < (uint32_t)W; q += nthr, ++na) {
+                const uint64_t t = ((uint64_t)P1[q] << 32 | P0[q]) + add[na];
+                P0[q] = (uint32_t)t;
+                P1[q] = (uint32_t)(t >> 32);
+            }
+            __syncthreads();
+        }
+        // column sums S_k: NC consecutive columns per thread
+        uint64_t lo[NC], Tk[NC];
+        uint32_t hi[NC];
+        const uint32_t k0 = tid * NC;
+        const bool mine = k0 < (uint32_t)W;
+        if (mine) {
+            uint32_t aw[NC];
 #pragma unroll
             for (int cc = 0; cc < NC; ++cc) {
-                pl[cc] = nl[cc] = 0;
-                ph[cc] = nh[cc] = 0;
-                bw[cc] = Bv[(k0 + cc) & (W - 1)];  // window at i = 0: b_{k0+cc}
+                lo[cc] = 0;
+                hi[cc] = 0;
+                aw[cc] = A[k0 + cc];  // window at j = 0: A2[k0 + cc]
+                Tk[cc] = (uint64_t)P1[k0 + cc] << 32 | P0[k0 + cc];
             }
-            for (uint32_t ii = 0; ii < (uint32_t)W; ++ii) {
-                const uint64_t av = A[ii];
+            for (uint32_t j = 0; j < (uint32_t)W; ++j) {
+                const uint64_t bj = Bv[j];
 #pragma unroll
                 for (int cc = 0; cc < NC; ++cc) {
-                    const uint64_t pr = av * bw[cc];
-                    if (ii <= k0 + cc) {
-                        const uint64_t s = pl[cc] + pr;
-                        ph[cc] += s < pr ? 1u : 0u;
-                        pl[cc] = s;
-                    } else {
-                        const uint64_t s = nl[cc] + pr;
-                        nh[cc] += s < pr ? 1u : 0u;
-                        nl[cc] = s;
-                    }
+                    const uint64_t pr = aw[cc] * bj;
+                    lo[cc] += pr;
+                    hi[cc] += lo[cc] < pr ? 1u : 0u;
                 }
-                // slide: next i needs b_{k0+cc-(i+1)}
+                // slide: the next j needs A2[(k0 + cc - j - 1) mod 2W]
 #pragma unroll
-                for (int cc = NC - 1; cc > 0; --cc) bw[cc] = bw[cc - 1];
-                bw[0] = Bv[(k0 - ii - 1u) & (W - 1)];
+                for (int cc = NC - 1; cc > 0; --cc) aw[cc] = aw[cc - 1];
+                aw[0] = A[(k0 - j - 1u) & (2u * W - 1u)];
             }
+        }
+        __syncthreads();  // every thread has read its T_k out of P0/P1
+        if (mine) {
 #pragma unroll
             for (int cc = 0; cc < NC; ++cc) {
                 const uint32_t k = k0 + cc;
-                P0[k] = (uint32_t)pl[cc];
-                P1[k] = (uint32_t)(pl[cc] >> 32);
-                P2[k] = ph[cc];
-                N0[k] = (uint32_t)nl[cc];
-                N1[k] = (uint32_t)(nl[cc] >> 32);
-                N2[k] = nh[cc];
+                // positive part S_k + T_k (96 bits), negative part 2^32 T_k
+                const uint64_t s0 = lo[cc] + Tk[cc];
+                P0[k] = (uint32_t)s0;
+                P1[k] = (uint32_t)(s0 >> 32);
+                P2[k] = hi[cc] + (s0 < Tk[cc] ? 1u : 0u);
+                N0[k] = 0u;
+                N1[k] = (uint32_t)Tk[cc];
+                N2[k] = (uint32_t)(Tk[cc] >> 32);
             }
         }
         __syncthreads();
@@ -289,7 +319,7 @@ template <int S, int C, bool TR>
 hipError_t pointwise_launch(uint64_t n, const uint32_t *a, const uint32_t *b, uint32_t *c, uint64_t cap,
                             uint32_t scale_e, hipStream_t st) {
     constexpr int W = S * C;
-    const size_t lds = (size_t)(8 * W + FChunk<S, C>::ESZ + 1) * 4;
+    const size_t lds = (size_t)pw_lds_words(W) * 4;
     if (lds > kLdsBudget) return hipErrorInvalidValue;
     static bool attr = false;
     hipError_t e = pointwise_attr(&fermat_pointwise_kernel<S, C, TR>, lds, attr);
@@ -308,7 +338,7 @@ hipError_t pointwise_launch(uint64_t n, const uint32_t *a, const uint32_t *b, ui
 template <int S, int C, bool TR>
 hipError_t pointwise_items_launch(uint64_t nitems, uint32_t *x, uint64_t cap, const uint4 *items, hipStream_t st) {
     constexpr int W = S * C;
-    const size_t lds = (size_t)(8 * W + FChunk<S, C>::ESZ + 1) * 4;
+    const size_t lds = (size_t)pw_lds_words(W) * 4;
     if (lds > kLdsBudget) return hipErrorInvalidValue;
     static bool attr = false;
     hipError_t e = pointwise_attr(&fermat_pointwise_items_kernel<S, C, TR>, lds, attr);
