@@ -86,9 +86,11 @@ __device__ __forceinline__ void pointwise_body(const uint32_t *a, uint32_t ta, c
             }
             __syncthreads();
         }
-        // column sums S_k: NC consecutive columns per thread
-        uint64_t lo[NC], Tk[NC];
-        uint32_t hi[NC];
+        // column sums S_k = 2^32 hi + lo: NC consecutive columns per thread.  Each
+        // step t = a b + lo fits in 64 bits ((2^32-1)^2 + 2^32-1 < 2^64): lo keeps
+        // its low word, hi (64 bits) gathers the high words; no carry tests.
+        uint64_t hi[NC], Tk[NC];
+        uint32_t lo[NC];
         const uint32_t k0 = tid * NC;
         const bool mine = k0 < (uint32_t)W;
         if (mine) {
@@ -100,13 +102,15 @@ __device__ __forceinline__ void pointwise_body(const uint32_t *a, uint32_t ta, c
                 aw[cc] = A[k0 + cc];  // window at j = 0: A2[k0 + cc]
                 Tk[cc] = (uint64_t)P1[k0 + cc] << 32 | P0[k0 + cc];
             }
+            // unrolled by the window width so that the slide below is register renaming
+#pragma unroll NC
             for (uint32_t j = 0; j < (uint32_t)W; ++j) {
                 const uint64_t bj = Bv[j];
 #pragma unroll
                 for (int cc = 0; cc < NC; ++cc) {
-                    const uint64_t pr = aw[cc] * bj;
-                    lo[cc] += pr;
-                    hi[cc] += lo[cc] < pr ? 1u : 0u;
+                    const uint64_t t = aw[cc] * bj + lo[cc];
+                    lo[cc] = (uint32_t)t;
+                    hi[cc] += t >> 32;
                 }
                 // slide: the next j needs A2[(k0 + cc - j - 1) mod 2W]
 #pragma unroll
@@ -120,10 +124,11 @@ __device__ __forceinline__ void pointwise_body(const uint32_t *a, uint32_t ta, c
             for (int cc = 0; cc < NC; ++cc) {
                 const uint32_t k = k0 + cc;
                 // positive part S_k + T_k (96 bits), negative part 2^32 T_k
-                const uint64_t s0 = lo[cc] + Tk[cc];
-                P0[k] = (uint32_t)s0;
-                P1[k] = (uint32_t)(s0 >> 32);
-                P2[k] = hi[cc] + (s0 < Tk[cc] ? 1u : 0u);
+                const uint64_t w0 = (uint64_t)lo[cc] + (uint32_t)Tk[cc];
+                const uint64_t w1 = (hi[cc] & 0xFFFFFFFFull) + (Tk[cc] >> 32) + (w0 >> 32);
+                P0[k] = (uint32_t)w0;
+                P1[k] = (uint32_t)w1;
+                P2[k] = (uint32_t)(hi[cc] >> 32) + (uint32_t)(w1 >> 32);
                 N0[k] = 0u;
                 N1[k] = (uint32_t)Tk[cc];
                 N2[k] = (uint32_t)(Tk[cc] >> 32);
