@@ -256,6 +256,46 @@ def batch_leg(T, torch, count=4096, train_count=32, heldout=16, replays=3, k1_st
     }
 
 
+def other_products(T, torch, reps=5):
+    """Latency of the other product workloads (median of `reps` runs, HIP events on the stream):
+    Z[x] 500 x 500 of 64 bits (ring 2^512+1, L = 2^10) and 3000 x 3000 of 2000 bits (2^4096+1, L = 2^13),
+    both latency-bound, and the Schoenhage-Nussbaumer product in (Z/mZ)[x], 500000 x 500000, K = 1024."""
+    import numpy as np
+    from synth import workloads as wl
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[len(ts) // 2]
+
+    out = {}
+    for c in (1, 2):
+        g, h = wl.zx_operands(c)
+        dg = torch.from_numpy(g.view(np.int32)).cuda()
+        dh = torch.from_numpy(h.view(np.int32)).cuda()
+        ow = (32 * (g.shape[1] + h.shape[1]) + (min(g.shape[0], h.shape[0]) - 1).bit_length() + 31) // 32
+        o = torch.empty((g.shape[0] + h.shape[0] - 1, ow), dtype=torch.int32, device="cuda")
+        ws = torch.empty(T.zx_mul_ss_workspace(g.shape[0], g.shape[1], h.shape[0], h.shape[1]), dtype=torch.uint8,
+                         device="cuda")
+        out["zx_%dx%d_%dbit_ms" % (g.shape[0], h.shape[0], wl.ZX_CASES[c]["bits"])] = round(
+            timed(lambda: T.zx_mul_ss(dg, dh, o, ws=ws)), 4)
+    m, g, h = wl.zmx_operands()
+    dg = torch.from_numpy(g.view(np.int64)).cuda()
+    dh = torch.from_numpy(h.view(np.int64)).cuda()
+    o = torch.empty(len(g) + len(h) - 1, dtype=torch.int64, device="cuda")
+    ws = torch.empty(T.zmx_mul_nussbaumer_workspace(len(g), len(h), 10), dtype=torch.uint8, device="cuda")
+    out["zmx_500000x500000_K1024_ms"] = round(timed(lambda: T.zmx_mul_nussbaumer(dg, dh, m, 10, o, ws=ws)), 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -351,6 +391,8 @@ def main():
     }
     del out, ws, dg, dh
     torch.cuda.empty_cache()
+    _progress("other products")
+    line["other_products"] = other_products(T, torch)
     if not args.no_batch:
         line["batch"] = batch_leg(T, torch)
     if not args.no_cpu_baseline:

@@ -429,11 +429,14 @@ static int ss_run(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uin
     uint32_t *B = A + sh.L * (sh.W + 1);
     // One product on its own: unless the caller chose the leaf, cap it so that a
     // pass still has about two leaf jobs per compute unit (larger leaves mean
-    // fewer passes, but a pass of fewer jobs than CUs leaves the GPU part idle).
+    // fewer passes, but a pass of fewer jobs than CUs leaves the GPU part idle);
+    // a small transform takes two passes of half its length rather than one
+    // workgroup running every level alone.
     tft_split sp = params ? params->split : tft_split{0, 0};
     if (!sp.leaf_log2) {
         const uint32_t fit = max_leaf_log2(&ring), fill = fill_log2();
-        sp.leaf_log2 = (sh.l > fill + 3) ? std::min(fit, std::max<uint32_t>(3, sh.l - fill)) : fit;
+        sp.leaf_log2 = (sh.l > fill + 3) ? std::min(fit, std::max<uint32_t>(3, sh.l - fill))
+                                         : std::min(fit, std::max<uint32_t>(1, (sh.l + 1) / 2));
     }
     const tft_split *split = &sp;
     tft_plan *pg = cached_plan(&ring, 0, sh.l, 0, sh.zg, sh.n, 0, split);
