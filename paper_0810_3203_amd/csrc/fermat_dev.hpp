@@ -91,6 +91,18 @@ struct FChunk {
         for (int j = 0; j < C; ++j) x[j * S + l] = v[j];
     }
 
+    // s[J..C) += c (SUB: -= c), c in {0, 1}; c becomes the carry (borrow) out.
+    // The carry passes limb J unless that limb is all ones (zero): the rest of
+    // the chain runs only if some lane of the wave still carries.
+    template <bool SUB, int J = 0>
+    __device__ __forceinline__ void propagate(uint32_t (&s)[C], uint32_t &c) const {
+        s[J] = SUB ? subb(s[J], 0u, c) : addc(s[J], 0u, c);
+        if (C > J + 1 && ballot(c != 0u) != 0ull) {
+#pragma unroll
+            for (int j = J + 1; j < C; ++j) s[j] = SUB ? subb(s[j], 0u, c) : addc(s[j], 0u, c);
+        }
+    }
+
     // Carry (borrow) cy out of each lane's chunk enters the next lane; repeat
     // while carries move.  Returns 1 if the segment's element overflowed
     // (carry or borrow out of limb W-1).
@@ -100,18 +112,41 @@ struct FChunk {
         uint64_t Cm = (G << 1) & ~FIRST;
         while (Cm != 0ull) {
             uint32_t c = lane_bit(Cm) ? 1u : 0u;
-            if (sub) {
-#pragma unroll
-                for (int j = 0; j < C; ++j) s[j] = subb(s[j], 0u, c);
-            } else {
-#pragma unroll
-                for (int j = 0; j < C; ++j) s[j] = addc(s[j], 0u, c);
-            }
+            if (sub)
+                propagate<true>(s, c);
+            else
+                propagate<false>(s, c);
             G = ballot(c != 0u);
             over |= G & LAST;
             Cm = (G << 1) & ~FIRST;
         }
         return seg_bit(over, S - 1);
+    }
+
+    // s = a + b (SUB: a - b) within each lane's chunk; returns the carry
+    // (borrow) out of the chunk.  The two halves of the chunk run as two
+    // interleaved chains (one carry waits on the other's instruction instead
+    // of a stall); the low half's carry then enters the high half.  The two
+    // carries out of the high half cannot both be set.
+    template <bool SUB>
+    __device__ __forceinline__ uint32_t chunk_addsub(uint32_t (&s)[C], const uint32_t (&a)[C],
+                                                     const uint32_t (&b)[C]) const {
+        if constexpr (C < 4) {
+            uint32_t c = 0;
+#pragma unroll
+            for (int j = 0; j < C; ++j) s[j] = SUB ? subb(a[j], b[j], c) : addc(a[j], b[j], c);
+            return c;
+        } else {
+            constexpr int H = C / 2;
+            uint32_t c0 = 0, c1 = 0;
+#pragma unroll
+            for (int j = 0; j < H; ++j) {
+                s[j] = SUB ? subb(a[j], b[j], c0) : addc(a[j], b[j], c0);
+                s[H + j] = SUB ? subb(a[H + j], b[H + j], c1) : addc(a[H + j], b[H + j], c1);
+            }
+            propagate<SUB, H>(s, c0);
+            return c0 | c1;
+        }
     }
 
     // s = a + b; returns the carry out of the element (0/1)
@@ -350,10 +385,7 @@ struct FermatOps : F {
         uint32_t a[C], b[C];
         this->ld(x0, a);
         this->ld(x1, b);
-        uint32_t cy = 0;
-#pragma unroll
-        for (int j = 0; j < C; ++j) a[j] = addc(a[j], b[j], cy);
-        const uint32_t ov = this->settle(a, cy, false);
+        const uint32_t ov = this->settle(a, this->template chunk_addsub<false>(a, a, b), false);
         const uint32_t top0 = this->canon(a, (int)ov + t0 + t1, 0, 0u);
         const uint32_t top1 = this->canon(d, -(int)bv, rt.sg * (t1 - t0), rt.t);
         this->st(x0, a);
