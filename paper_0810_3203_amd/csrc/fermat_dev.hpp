@@ -91,18 +91,6 @@ struct FChunk {
         for (int j = 0; j < C; ++j) x[j * S + l] = v[j];
     }
 
-    // s[J..C) += c (SUB: -= c), c in {0, 1}; c becomes the carry (borrow) out.
-    // The carry passes limb J unless that limb is all ones (zero): the rest of
-    // the chain runs only if some lane of the wave still carries.
-    template <bool SUB, int J = 0>
-    __device__ __forceinline__ void propagate(uint32_t (&s)[C], uint32_t &c) const {
-        s[J] = SUB ? subb(s[J], 0u, c) : addc(s[J], 0u, c);
-        if (C > J + 1 && ballot(c != 0u) != 0ull) {
-#pragma unroll
-            for (int j = J + 1; j < C; ++j) s[j] = SUB ? subb(s[j], 0u, c) : addc(s[j], 0u, c);
-        }
-    }
-
     // Carry (borrow) cy out of each lane's chunk enters the next lane; repeat
     // while carries move.  Returns 1 if the segment's element overflowed
     // (carry or borrow out of limb W-1).
@@ -112,41 +100,18 @@ struct FChunk {
         uint64_t Cm = (G << 1) & ~FIRST;
         while (Cm != 0ull) {
             uint32_t c = lane_bit(Cm) ? 1u : 0u;
-            if (sub)
-                propagate<true>(s, c);
-            else
-                propagate<false>(s, c);
+            if (sub) {
+#pragma unroll
+                for (int j = 0; j < C; ++j) s[j] = subb(s[j], 0u, c);
+            } else {
+#pragma unroll
+                for (int j = 0; j < C; ++j) s[j] = addc(s[j], 0u, c);
+            }
             G = ballot(c != 0u);
             over |= G & LAST;
             Cm = (G << 1) & ~FIRST;
         }
         return seg_bit(over, S - 1);
-    }
-
-    // s = a + b (SUB: a - b) within each lane's chunk; returns the carry
-    // (borrow) out of the chunk.  The two halves of the chunk run as two
-    // interleaved chains (one carry waits on the other's instruction instead
-    // of a stall); the low half's carry then enters the high half.  The two
-    // carries out of the high half cannot both be set.
-    template <bool SUB>
-    __device__ __forceinline__ uint32_t chunk_addsub(uint32_t (&s)[C], const uint32_t (&a)[C],
-                                                     const uint32_t (&b)[C]) const {
-        if constexpr (C < 4) {
-            uint32_t c = 0;
-#pragma unroll
-            for (int j = 0; j < C; ++j) s[j] = SUB ? subb(a[j], b[j], c) : addc(a[j], b[j], c);
-            return c;
-        } else {
-            constexpr int H = C / 2;
-            uint32_t c0 = 0, c1 = 0;
-#pragma unroll
-            for (int j = 0; j < H; ++j) {
-                s[j] = SUB ? subb(a[j], b[j], c0) : addc(a[j], b[j], c0);
-                s[H + j] = SUB ? subb(a[H + j], b[H + j], c1) : addc(a[H + j], b[H + j], c1);
-            }
-            propagate<SUB, H>(s, c0);
-            return c0 | c1;
-        }
     }
 
     // s = a + b; returns the carry out of the element (0/1)
@@ -256,31 +221,35 @@ struct Rot {
     }
 };
 
-// (a & m) | (b & ~m) as one v_bfi_b32.  Written as an instruction because
-// with m known to be all ones or zero the compiler otherwise turns the merge
-// into compare + select pairs through VCC, each pair with hazard wait states.
-// Registers only (no memory access).
-__device__ __forceinline__ uint32_t bfi(uint32_t m, uint32_t a, uint32_t b) {
-    uint32_t r;
-    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(m), "v"(a), "v"(b));
-    return r;
-}
+// Per-lane masks of a rotation: limb j of the lane's chunk takes its bits
+// below position t (the wrapped part) from mask low(j) = all ones for j < jq,
+// the partial mask pm for j = jq, zero above, with jq = q - l*C.  Built once
+// per operation as two bit sets, then one sign-extending bit extract and one
+// and-or per limb (no compare/select through lane masks).
+template <int C>
+struct RotMask {
+    using B = typename std::conditional<(C > 32), uint64_t, uint32_t>::type;
+    B lt, eq;  // bit j: j < jq; j == jq
+    uint32_t pm;
 
-// Word i of a lane's rotation window lies in the wrapped part iff i <= jw.
-// Bits 0..63 of lo:hi hold that test for words 0..63 (one sign-extending bit
-// extract per word); the last word of a 64-limb chunk's window (i = 64) is
-// compared directly.
-struct WrapBits {
-    uint32_t lo, hi;
-    int jw;
-    __device__ __forceinline__ explicit WrapBits(int jw_) : jw(jw_) {
-        lo = jw < 0 ? 0u : (jw >= 31 ? ~0u : (2u << jw) - 1u);
-        hi = jw < 32 ? 0u : (jw >= 63 ? ~0u : (2u << (jw - 32)) - 1u);
+    __device__ __forceinline__ RotMask(int jq, uint32_t pm_) : pm(pm_) {
+        constexpr int NB = C > 32 ? 64 : 32;
+        lt = jq >= C ? ~B(0) : (jq <= 0 ? B(0) : ((B(1) << jq) - B(1)));
+        eq = (jq >= 0 && jq < C) ? (B(1) << jq) : B(0);
+        (void)NB;
     }
-    template <int I>
-    __device__ __forceinline__ uint32_t mask() const {  // all ones if word I is wrapped
-        if constexpr (I >= 64) return I <= jw ? ~0u : 0u;
-        return (uint32_t)__builtin_amdgcn_sbfe((int32_t)(I < 32 ? lo : hi), I & 31, 1);
+    template <int J>
+    __device__ __forceinline__ static uint32_t ext(B v) {  // 0 or all ones from bit J
+        if constexpr (C > 32) {
+            const uint32_t w = J < 32 ? (uint32_t)v : (uint32_t)(v >> 32);
+            return (uint32_t)(((int32_t)(w << (31 - (J & 31)))) >> 31);
+        } else {
+            return (uint32_t)(((int32_t)(v << (31 - J))) >> 31);
+        }
+    }
+    template <int J>
+    __device__ __forceinline__ uint32_t low() const {
+        return ext<J>(lt) | (ext<J>(eq) & pm);
     }
 };
 
@@ -309,47 +278,27 @@ struct FermatOps : F {
         if constexpr (F::S == 64 && C > 1) {
             const uint32_t row0 = __builtin_amdgcn_readfirstlane((0u - qp) & (uint32_t)(C - 1));
             const uint32_t col0 = ((this->l * C - qp) & (uint32_t)(W - 1)) / C, col1 = (col0 + 1u) & 63u;
-            // two bases; limb i reads base + 64 i (an immediate offset) from the
-            // first while row0 + i < C, from the second after (pB + 64 i is in
-            // the element wherever it is read)
-            const uint32_t *pA = x + (row0 * 64u + col0);
-            const uint32_t *pB = x + (int32_t)(row0 * 64u + col1) - (int32_t)(64u * C);
+            const uint32_t oA = row0 * 64u + col0;
+            const uint32_t oB = row0 * 64u + col1 - 64u * C;  // used only where oB + 64 i >= 0
 #pragma unroll
-            for (int i = 0; i <= C; ++i) src[i] = ((uint32_t)i + row0 < (uint32_t)C ? pA : pB)[64 * i];
+            for (int i = 0; i <= C; ++i) src[i] = x[((uint32_t)i + row0 < (uint32_t)C ? oA : oB) + 64u * i];
         } else {
 #pragma unroll
             for (int i = 0; i <= C; ++i) src[i] = x[F::addr((this->l * C - qp + (uint32_t)i) & (uint32_t)(W - 1))];
         }
     }
 
-    // Last window word of the lane that lies in the wrapped part: the rotated
-    // limb j = alignbit(src[j+1], src[j]) takes its bits below t from src[j]
-    // and the rest from src[j+1], so with jw = q - l C (one less when t is a
-    // multiple of 32) limb j wraps entirely for j < jw, its low t % 32 bits for
-    // j == jw (src[j] wrapped, src[j+1] not) and not at all for j > jw.
-    __device__ __forceinline__ int wrap_word(const Rot<F> &rt) const {
-        return (int)rt.q - (int)(this->l * C) - (rt.c == 0u ? 1 : 0);
-    }
-
     template <bool NEG>
     __device__ __forceinline__ uint32_t rot_sub_impl(const uint32_t *x, const Rot<F> &rt, uint32_t (&v)[C]) const {
         uint32_t src[C + 1];
         rot_words(x, rt.qp, src);
-        const WrapBits wb(wrap_word(rt));
-        // Lo (bits that stay below 2^N) and Hi (wrapped bits) as two windows
-        // with the other part's words zeroed
-        uint32_t lo[C + 1], hi[C + 1];
-        static_for<0, C + 1>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            const uint32_t m = wb.template mask<i>();
-            lo[i] = bfi(m, 0u, src[i]);
-            hi[i] = bfi(m, src[i], 0u);
-        });
+        const RotMask<C> mk((int)rt.q - (int)(this->l * C), rt.pm);
         uint32_t b = 0;
         static_for<0, C>([&](auto jc) {
             constexpr int j = decltype(jc)::value;
-            const uint32_t lp = __builtin_amdgcn_alignbit(lo[j + 1], lo[j], rt.c);
-            const uint32_t hp = __builtin_amdgcn_alignbit(hi[j + 1], hi[j], rt.c);
+            const uint32_t r = __builtin_amdgcn_alignbit(src[j + 1], src[j], rt.c);
+            const uint32_t low = mk.template low<j>();
+            const uint32_t hp = r & low, lp = r & ~low;
             v[j] = NEG ? subb(hp, lp, b) : subb(lp, hp, b);
         });
         return this->settle(v, b, true);
@@ -384,21 +333,14 @@ struct FermatOps : F {
             uint32_t s0[C + 1], s1[C + 1];
             rot_words(x0, rt.qp, s0);
             rot_words(x1, rt.qp, s1);
-            // A and B as windows of words: a word in the wrapped part comes
-            // from the other operand (wrap_word)
-            const WrapBits wb(wrap_word(rt));
-            static_for<0, C + 1>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                const uint32_t m = wb.template mask<i>();
-                const uint32_t a = bfi(m, s1[i], s0[i]);
-                const uint32_t b = bfi(m, s0[i], s1[i]);
-                s0[i] = a;
-                s1[i] = b;
-            });
+            const RotMask<C> mk((int)rt.q - (int)(this->l * C), rt.pm);
             static_for<0, C>([&](auto jc) {
                 constexpr int j = decltype(jc)::value;
-                const uint32_t A = __builtin_amdgcn_alignbit(s0[j + 1], s0[j], rt.c);
-                const uint32_t B = __builtin_amdgcn_alignbit(s1[j + 1], s1[j], rt.c);
+                const uint32_t r0 = __builtin_amdgcn_alignbit(s0[j + 1], s0[j], rt.c);
+                const uint32_t r1 = __builtin_amdgcn_alignbit(s1[j + 1], s1[j], rt.c);
+                const uint32_t low = mk.template low<j>();
+                const uint32_t A = (r1 & low) | (r0 & ~low);
+                const uint32_t B = (r0 & low) | (r1 & ~low);
                 d[j] = NEG ? subb(B, A, bd) : subb(A, B, bd);
             });
         }
@@ -408,7 +350,10 @@ struct FermatOps : F {
         uint32_t a[C], b[C];
         this->ld(x0, a);
         this->ld(x1, b);
-        const uint32_t ov = this->settle(a, this->template chunk_addsub<false>(a, a, b), false);
+        uint32_t cy = 0;
+#pragma unroll
+        for (int j = 0; j < C; ++j) a[j] = addc(a[j], b[j], cy);
+        const uint32_t ov = this->settle(a, cy, false);
         const uint32_t top0 = this->canon(a, (int)ov + t0 + t1, 0, 0u);
         const uint32_t top1 = this->canon(d, -(int)bv, rt.sg * (t1 - t0), rt.t);
         this->st(x0, a);

@@ -27,31 +27,11 @@ constexpr uint32_t kLeafStaticLds = 0u;  // no static LDS in fermat_leaf_kernel
 constexpr int CB = 8;
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// 16 bytes per lane from global memory straight into LDS at dst + 16 * lane
-// (dst the same for the whole wave); completion is counted like a load.
-__device__ __forceinline__ void load_lds_x4(const uint32_t *src, uint32_t *dst) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
-#endif
-}
-
 template <class F, bool IN, bool TR>
 __device__ __forceinline__ void copy_cells(uint32_t *sm, uint32_t *x, const Job &J, uint32_t n, uint32_t tid,
                                            uint32_t nthr) {
     constexpr int W = F::W, C = F::C;
-    if constexpr (IN && TR && F::S == 64 && W % 256 == 0) {
-        // the global cell has the LDS order and whole 1 KB pieces: each wave
-        // loads pieces straight into LDS (16 bytes per lane), all in flight at once
-        constexpr uint32_t PER = W / 256;
-        const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6), nw = nthr >> 6, lane = tid & 63u;
-        const uint32_t total = n * PER;
-        for (uint32_t c = wave; c < total; c += nw) {
-            const uint32_t cell = c / PER, part = c % PER;
-            const uint32_t *src = x + (J.base + (uint64_t)cell * J.stride) * W + part * 256u + lane * 4u;
-            load_lds_x4(src, sm + cell * F::ESZ + part * 256u);
-        }
-        __builtin_amdgcn_s_waitcnt(0);  // this wave's pieces are in LDS (the caller's barrier covers the rest)
-    } else if constexpr (TR || F::S < 64) {
+    if constexpr (TR || F::S < 64) {
         // the global cell has the LDS order: a straight copy
         if constexpr (W % 4 == 0) {
             constexpr uint32_t WQ = W / 4;
@@ -150,16 +130,14 @@ __device__ __forceinline__ void copy_cells(uint32_t *sm, uint32_t *x, const Job 
 
 // Base-case sets a leaf kernel is compiled for.  Keeping the rare boundary
 // cases out of the hot kernels keeps their register allocation within 256
-// VGPRs (no spills) for the largest elements: the TFT set, the ITFT cases of
-// full and most truncated columns, every ITFT case, everything.
-enum LeafSet : int { SET_TFT = 0, SET_ITFT = 1, SET_ALL = 2, SET_ITFT_ALL = 3 };
+// VGPRs (no spills) for the largest elements.
+enum LeafSet : int { SET_TFT = 0, SET_ITFT = 1, SET_ALL = 2 };
 constexpr uint32_t kTftOps = (1u << OP_T22) | (1u << OP_T21) | (1u << OP_T12);
 constexpr uint32_t kItftOps = (1u << OP_I2) | (1u << OP_I1F1Z2) | (1u << OP_I1F0Z2) | (1u << OP_I1F0Z1);
-constexpr uint32_t kItftAllOps = kItftOps | (1u << OP_I1F1Z1) | (1u << OP_I0Z2) | (1u << OP_I0Z1);
 
 template <int V>
 constexpr bool set_has(uint32_t code) {
-    return V == SET_ALL || (((V == SET_TFT ? kTftOps : V == SET_ITFT ? kItftOps : kItftAllOps) >> code) & 1u);
+    return V == SET_ALL || (V == SET_TFT ? ((kTftOps >> code) & 1u) : ((kItftOps >> code) & 1u));
 }
 
 template <int S, int C, int V, bool TR>
@@ -175,33 +153,20 @@ __device__ __forceinline__ void leaf_body(const Job *__restrict__ jobs, const Le
     const Job J = jobs[job_offset + blockIdx.x];
     const LeafProg P = progs[J.prog];
     const uint32_t tid = threadIdx.x, nthr = blockDim.x;
-    const FermatOps<F> B;
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6), nwaves = nthr >> 6;
-    const uint32_t g = B.lane / S;
-    const uint32_t jfirst = wave * G + g;
-
-    // Descriptors run ahead of the butterflies: a step's descriptor is fetched
-    // two steps early and this lane's first op of a step one step early, so
-    // their latency overlaps the cell copy and the previous step's work.
-    const LeafStep *psteps = steps + P.step_begin;
-    LeafStep cur = P.step_count > 0 ? psteps[0] : LeafStep{0u, 0u};
-    LeafStep nxt = P.step_count > 1 ? psteps[1] : LeafStep{0u, 0u};
-    LeafOp ocur = jfirst < cur.op_count ? ops[cur.op_begin + jfirst] : LeafOp{0u, 0u};
 
     copy_cells<F, true, TR>(sm, x, J, J.nload, tid, nthr);
     for (uint32_t t = tid; t < J.nload; t += nthr) stop[t] = x[cap * W + J.base + (uint64_t)t * J.stride];
     __syncthreads();
 
+    const FermatOps<F> B;
+    const uint32_t wave = tid >> 6, nwaves = nthr >> 6;
+    const uint32_t g = B.lane / S;
     for (uint32_t st = 0; st < P.step_count; ++st) {
-        const LeafStep LS = cur;
-        const LeafOp ofirst = ocur;
-        ocur = jfirst < nxt.op_count ? ops[nxt.op_begin + jfirst] : LeafOp{0u, 0u};
-        cur = nxt;
-        nxt = st + 2 < P.step_count ? psteps[st + 2] : LeafStep{0u, 0u};
+        const LeafStep LS = steps[P.step_begin + st];
         for (uint32_t jb = wave * G; jb < LS.op_count; jb += nwaves * G) {
             const uint32_t j = jb + g;
             if (j < LS.op_count) {
-                const LeafOp o = jb == wave * G ? ofirst : ops[LS.op_begin + j];
+                const LeafOp o = ops[LS.op_begin + j];
                 const uint32_t code = o.w0 & 15u;
                 const uint32_t i0 = (o.w0 >> 4) & 16383u, i1 = (o.w0 >> 18) & 16383u;
                 const uint32_t e =
@@ -302,9 +267,6 @@ struct LeafLaunch {
     if ((opmask & ~kItftOps) == 0u)
         return leaf_launch_set<S, C, SET_ITFT, TR>(nwaves, njobs, lds_cells, jobs, job_offset, progs, steps, ops, x, cap,
                                                ord_mask, st);
-    if ((opmask & ~kItftAllOps) == 0u)
-        return leaf_launch_set<S, C, SET_ITFT_ALL, TR>(nwaves, njobs, lds_cells, jobs, job_offset, progs, steps, ops, x,
-                                                   cap, ord_mask, st);
     return leaf_launch_set<S, C, SET_ALL, TR>(nwaves, njobs, lds_cells, jobs, job_offset, progs, steps, ops, x, cap,
                                           ord_mask, st);
 }
