@@ -287,26 +287,42 @@ __global__ void fermat_unpack1_kernel(const UnpackDesc *__restrict__ descs, Unpa
 
 // Unpack with k > 1: the product cell m holds slots 0..2k-2 of width ws limbs;
 // coefficient t = m k + j is slot j of cell m plus slot j + k of cell m - 1.
-__global__ void fermat_unpackk_kernel(const UnpackDesc *__restrict__ descs, UnpackDesc inl,
-                                      const uint32_t *__restrict__ x, uint32_t W, uint32_t tr) {
+// One wave per coefficient and a lane per limb (64 limbs per round): limb i is
+// v_i = s0_i + s1_i (< 2^33 - 1, so it emits at most one carry) plus the carry
+// from the limbs below.  With G the lanes whose v_i carries out, P the lanes
+// whose low word is all ones (they pass a carry on) and c the carry into the
+// round, the carries into the lanes are the bits of (a + G + c) ^ a ^ G with
+// a = G | P, and the carry out of the round is that sum's overflow.  Loads of
+// one slot and the output row are contiguous per wave.
+__global__ void __launch_bounds__(256) fermat_unpackk_kernel(const UnpackDesc *__restrict__ descs, UnpackDesc inl,
+                                                             const uint32_t *__restrict__ x, uint32_t W,
+                                                             uint32_t tr) {
     const UnpackDesc d = descs ? descs[blockIdx.y] : inl;
-    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < d.len_out;
-         t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t lane = threadIdx.x & 63u, wpb = blockDim.x >> 6;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (uint64_t t = (uint64_t)blockIdx.x * wpb + wave; t < d.len_out; t += (uint64_t)gridDim.x * wpb) {
         const uint64_t m = t / d.k;
         const uint32_t j = (uint32_t)(t % d.k);
         // slot j of cell m and slot j + k of cell m - 1 (limbs j ws + i, (j + k) ws + i)
-        const uint32_t *s0 = (m < d.ncells) ? x + (d.cell0 + m) * W : nullptr;
-        const uint32_t *s1 = (m >= 1 && j + 1 < d.k && m - 1 < d.ncells) ? x + (d.cell0 + m - 1) * W : nullptr;
+        const bool h0 = m < d.ncells, h1 = m >= 1 && j + 1 < d.k && m - 1 < d.ncells;
+        const uint32_t *s0 = x + (d.cell0 + m) * W;
+        const uint32_t *s1 = h1 ? x + (d.cell0 + m - 1) * W : x;
         const uint32_t k0 = j * d.ws, k1 = (j + d.k) * d.ws;
         uint32_t *o = d.out + t * d.olimbs;
         uint64_t c = 0;
-        for (uint32_t i = 0; i < d.olimbs; ++i) {
+        for (uint32_t i0 = 0; i0 < d.olimbs; i0 += 64u) {
+            const uint32_t i = i0 + lane;
+            uint64_t v = 0;
             if (i < d.ws) {
-                c += (s0 ? s0[tr ? tpos(k0 + i, W) : k0 + i] : 0u);
-                c += (s1 ? s1[tr ? tpos(k1 + i, W) : k1 + i] : 0u);
+                if (h0) v += s0[tr ? tpos(k0 + i, W) : k0 + i];
+                if (h1) v += s1[tr ? tpos(k1 + i, W) : k1 + i];
             }
-            o[i] = (uint32_t)c;
-            c >>= 32;
+            const uint32_t lo = (uint32_t)v;
+            const uint64_t G = ballot((v >> 32) != 0ull), P = ballot(lo == 0xFFFFFFFFu);
+            const uint64_t a = G | P, s = a + G, s2 = s + c;
+            const uint64_t cin = s2 ^ a ^ G;
+            if (i < d.olimbs) o[i] = lo + (uint32_t)((cin >> lane) & 1ull);
+            c = (s < a || s2 < s) ? 1ull : 0ull;
         }
     }
 }
@@ -425,7 +441,7 @@ hipError_t launch_fermat_unpack(uint32_t W, const UnpackDesc *descs, uint32_t nd
         hipLaunchKernelGGL(fermat_unpack1_kernel, dim3((uint32_t)blocks, ndesc), dim3(256), 0, st, descs, inl, x, cap,
                            W, tr);
     } else {
-        uint64_t blocks = (max_len + 255) / 256;
+        uint64_t blocks = (max_len + 3) / 4;  // four waves per block, a wave per coefficient
         if (blocks > 4096) blocks = 4096;
         hipLaunchKernelGGL(fermat_unpackk_kernel, dim3((uint32_t)blocks, ndesc), dim3(256), 0, st, descs, inl, x, W,
                            tr);
