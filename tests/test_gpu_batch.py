@@ -86,6 +86,24 @@ def test_bundled_k_full(coracle, k):
         assert np.array_equal(got, _oracle_full(coracle, r)), "k=%d %dx%d" % (k, lg, lh)
 
 
+@pytest.mark.parametrize("k,bits", [(2, 1000), (3, 1000), (8, 2016), (4, 4000)])
+def test_bundled_carry_runs(coracle, k, bits):
+    """All-ones coefficients: the slot sums of the bundled unpack carry through
+    long runs of all-ones limbs, across rounds of 64 output limbs."""
+    for lg, lh in [(7, 9), (40, 33)]:
+        w = (bits + 31) // 32
+        g = np.full((lg, w), 0xFFFFFFFF, dtype=np.uint32)
+        h = np.full((lh, w), 0xFFFFFFFF, dtype=np.uint32)
+        top = bits - 32 * (w - 1)
+        if top < 32:
+            g[:, -1] = (1 << top) - 1
+            h[:, -1] = (1 << top) - 1
+        h[1::3] = 0  # zero coefficients between the full ones
+        r = _Req(g, h, T.SSParams(0, 0, T.Split(0, 0), k))
+        note("zx_mul_ss all-ones k=%d %dx%d %d bits (%d output limbs)" % (k, lg, lh, bits, r.ow))
+        assert np.array_equal(r.one_at_a_time(), _oracle_full(coracle, r)), "k=%d %dx%d" % (k, lg, lh)
+
+
 def test_bundled_k_with_split_and_ring(coracle):
     g, h = _operands(99, 200, 150, 64)
     for p in [T.SSParams(0, 0, T.Split(2, 0), 2), T.SSParams(0, 0, T.Split(1, 2), 4),
