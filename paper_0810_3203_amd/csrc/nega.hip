@@ -189,14 +189,31 @@ __device__ __forceinline__ uint64_t redc(uint64_t lo, uint64_t hi, uint64_t m, u
     return t >= m ? t - m : t;
 }
 
-constexpr int NP_COLS = 4;
-constexpr int NP_GROUP = 4;  // products per 128-bit partial sum: 4 m^2 < m 2^64 for m < 2^62
+constexpr int NP_COLS = 4;     // columns per thread up to K = 1024 (256 threads); K / 256 above
+constexpr int NP_GROUP = 16;  // products per 128-bit partial sum: 16 m^2 < 2^128 for m < 2^62
 
+// a b as a 128-bit value (hi:lo) for a, b < 2^63, from four 32x32 -> 64 multiply-adds
+__device__ __forceinline__ void mul128(uint64_t a, uint64_t b, uint64_t &lo, uint64_t &hi) {
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+    const uint64_t p00 = (uint64_t)a0 * b0;
+    const uint64_t t1 = (uint64_t)a0 * b1 + (p00 >> 32);
+    const uint64_t t2 = (uint64_t)a1 * b0 + (uint32_t)t1;
+    lo = (t2 << 32) | (uint32_t)p00;
+    hi = (uint64_t)a1 * b1 + (t1 >> 32) + (t2 >> 32);
+}
+
+// c_k = sum_i a_i b_{k-i} - sum_{i>k} a_i b_{k-i+K}  (mod m, y^K = -1), times 2^-scale.
+// Each thread owns NP_COLS consecutive columns and slides a register window
+// over B2 = [b, m - b] (the wrapped terms enter negated, so every product is
+// unsigned): the word entering the window is negated when its index wraps.
+// Products are summed in 128 bits and reduced (Montgomery, R = 2^64) every
+// NP_GROUP terms after the high word is brought below m.
 template <int K>
 __global__ void __launch_bounds__(256) nega_pointwise_kernel(const uint64_t *__restrict__ a,
                                                              const uint64_t *__restrict__ b, uint64_t *c, uint64_t m,
                                                              uint64_t minv, uint64_t cfac) {
-    __shared__ uint64_t A[K], B[K];
+    extern __shared__ uint64_t nega_pw_sm[];  // A (K words) then B (K words)
+    uint64_t *A = nega_pw_sm, *B = nega_pw_sm + K;
     const uint64_t i = blockIdx.x;
     const uint32_t tid = threadIdx.x, nthr = blockDim.x;
     for (uint32_t q = tid; q < (uint32_t)K; q += nthr) {
@@ -204,50 +221,50 @@ __global__ void __launch_bounds__(256) nega_pointwise_kernel(const uint64_t *__r
         B[q] = b[i * K + q];
     }
     __syncthreads();
-    constexpr int NC = K < NP_COLS ? K : NP_COLS;
+    constexpr int NC = K < NP_COLS ? K : (K > 256 * NP_COLS ? K / 256 : NP_COLS);
     uint64_t res[NC];
     bool have = false;
-    uint32_t k0 = tid * NC;
+    const uint32_t k0 = tid * NC;
     if (k0 < (uint32_t)K) {
         have = true;
-        uint64_t pr[NC], nr[NC], plo[NC], phi[NC], nlo[NC], nhi[NC], bw[NC];
+        const uint64_t m2 = 2 * m;
+        uint64_t lo[NC], hi[NC], r[NC], bw[NC];
 #pragma unroll
         for (int cc = 0; cc < NC; ++cc) {
-            pr[cc] = nr[cc] = plo[cc] = phi[cc] = nlo[cc] = nhi[cc] = 0;
-            bw[cc] = B[(k0 + cc) & (K - 1)];
+            lo[cc] = hi[cc] = r[cc] = 0;
+            bw[cc] = B[k0 + cc];  // window at i = 0: B2[k0 + cc]
         }
         for (uint32_t ii = 0; ii < (uint32_t)K; ++ii) {
             const uint64_t av = A[ii];
 #pragma unroll
             for (int cc = 0; cc < NC; ++cc) {
-                const uint64_t lo = av * bw[cc], hi = __umul64hi(av, bw[cc]);
-                if (ii <= k0 + cc) {
-                    const uint64_t s = plo[cc] + lo;
-                    phi[cc] += hi + (s < lo ? 1u : 0u);
-                    plo[cc] = s;
-                } else {
-                    const uint64_t s = nlo[cc] + lo;
-                    nhi[cc] += hi + (s < lo ? 1u : 0u);
-                    nlo[cc] = s;
-                }
+                uint64_t pl, ph;
+                mul128(av, bw[cc], pl, ph);
+                lo[cc] += pl;
+                hi[cc] += ph + (lo[cc] < pl ? 1u : 0u);
             }
             if ((ii & (NP_GROUP - 1)) == NP_GROUP - 1 || ii + 1 == (uint32_t)K) {
 #pragma unroll
                 for (int cc = 0; cc < NC; ++cc) {
-                    pr[cc] = madd(pr[cc], redc(plo[cc], phi[cc], m, minv), m);
-                    nr[cc] = madd(nr[cc], redc(nlo[cc], nhi[cc], m, minv), m);
-                    plo[cc] = phi[cc] = nlo[cc] = nhi[cc] = 0;
+                    uint64_t h = hi[cc];  // < 16 m^2 / 2^64 < 4 m
+                    h = h >= m2 ? h - m2 : h;
+                    h = h >= m ? h - m : h;
+                    r[cc] = madd(r[cc], redc(lo[cc], h, m, minv), m);
+                    lo[cc] = hi[cc] = 0;
                 }
             }
 #pragma unroll
             for (int cc = NC - 1; cc > 0; --cc) bw[cc] = bw[cc - 1];
-            bw[0] = B[(k0 - ii - 1u) & (K - 1)];
+            // column k0 at step ii + 1 needs B2[(k0 - ii - 1) mod 2K]
+            const uint64_t bv = B[(k0 - ii - 1u) & (K - 1u)];
+            bw[0] = ii + 1u <= k0 ? bv : m - bv;
         }
 #pragma unroll
         for (int cc = 0; cc < NC; ++cc) {
-            // (pos - neg) 2^-64 -> times cfac = 2^128 2^-scale, reduced once more
-            const uint64_t d = msub(pr[cc], nr[cc], m);
-            res[cc] = redc(d * cfac, __umul64hi(d, cfac), m, minv);
+            // r = (sum) 2^-64; times cfac = 2^128 2^-scale, reduced once more
+            uint64_t pl, ph;
+            mul128(r[cc], cfac, pl, ph);
+            res[cc] = redc(pl, ph, m, minv);
         }
     }
     __syncthreads();  // c may alias a or b
@@ -317,14 +334,23 @@ hipError_t nega_pw_launch(uint64_t m, uint64_t n, const uint64_t *a, const uint6
     const uint64_t inv2 = (m + 1) / 2;
     for (uint32_t t = 0; t < scale_log2; ++t) r = (r * inv2) % m;
     const uint64_t cfac = (uint64_t)r;
-    uint32_t thr = (K + NP_COLS - 1) / NP_COLS;
+    constexpr int NC = K < NP_COLS ? K : (K > 256 * NP_COLS ? K / 256 : NP_COLS);
+    uint32_t thr = (K + NC - 1) / NC;
     thr = thr < 64 ? 64 : (thr > 256 ? 256 : thr);
     thr = (thr + 63) / 64 * 64;
-    if ((uint32_t)K > thr * NP_COLS) return hipErrorInvalidValue;
+    if ((uint32_t)K > thr * NC) return hipErrorInvalidValue;
+    const size_t lds = 2ull * K * sizeof(uint64_t);
+    static bool attr = false;
+    if (!attr && lds >= 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&nega_pointwise_kernel<K>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
     const uint64_t per = kMaxGridX / thr;
     for (uint64_t i0 = 0; i0 < n; i0 += per) {
         const uint64_t nb = n - i0 < per ? n - i0 : per;
-        hipLaunchKernelGGL((nega_pointwise_kernel<K>), dim3((uint32_t)nb), dim3(thr), 0, st, a + i0 * K, b + i0 * K,
+        hipLaunchKernelGGL((nega_pointwise_kernel<K>), dim3((uint32_t)nb), dim3(thr), lds, st, a + i0 * K, b + i0 * K,
                            c + i0 * K, m, minv, cfac);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -373,6 +399,8 @@ hipError_t launch_nega_pointwise(uint32_t K, uint64_t m, uint64_t n, const uint6
         case 256: return nega_pw_launch<256>(m, n, a, b, c, scale_log2, st);
         case 512: return nega_pw_launch<512>(m, n, a, b, c, scale_log2, st);
         case 1024: return nega_pw_launch<1024>(m, n, a, b, c, scale_log2, st);
+        case 2048: return nega_pw_launch<2048>(m, n, a, b, c, scale_log2, st);
+        case 4096: return nega_pw_launch<4096>(m, n, a, b, c, scale_log2, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -194,6 +194,21 @@ def test_nega_transforms(K):
             assert nega_from_device(x, K, n + f) == expect
 
 
+@pytest.mark.parametrize("K", [2, 1024, 4096])
+def test_nega_pointwise_extreme_values(K):
+    """Coefficients m - 1 and 0 (a zero entering the negated wrap is m), 62-bit modulus."""
+    m = (1 << 62) - 57
+    ring = O.NegaRing(K, m)
+    a = [[m - 1] * K, [m - 1 if j % 3 else 0 for j in range(K)], [0] * K]
+    b = [[0 if j % 2 else m - 1 for j in range(K)], [m - 1] * K, [m - 1] * K]
+    note("nega pointwise extreme values K=%d" % K)
+    da, db = nega_to_device(a, K, 3, torch), nega_to_device(b, K, 3, torch)
+    dc = torch.zeros_like(da)
+    T.pointwise_mul(T.nega_ring(K, m), 3, da, db, dc, 3, 5)
+    torch.cuda.synchronize()
+    assert nega_from_device(dc, K, 3) == O.pointwise(ring, a, b, 5)
+
+
 @pytest.mark.parametrize("K", [2, 16, 64, 1024])
 def test_nega_pointwise(K):
     rng = random.Random(K + 5)
