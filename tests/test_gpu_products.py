@@ -116,7 +116,8 @@ def _zmx_gpu(g, h, m, log2K):
 
 
 @pytest.mark.parametrize("lg,lh,log2K,m", [(1, 1, 1, 3), (5, 9, 3, 1000003), (300, 200, 5, (1 << 62) - 57),
-                                           (3000, 2000, 7, (1 << 61) + 1), (1024, 1024, 10, 12345677)])
+                                           (3000, 2000, 7, (1 << 61) + 1), (1024, 1024, 10, 12345677),
+                                           (5000, 3000, 11, (1 << 62) - 57), (6000, 9000, 12, (1 << 62) - 57)])
 def test_zmx_small_full(coracle, lg, lh, log2K, m):
     rng = np.random.default_rng(lg + lh)
     g = (rng.integers(0, 1 << 62, size=lg, dtype=np.uint64) % np.uint64(m)).astype(np.uint64)
