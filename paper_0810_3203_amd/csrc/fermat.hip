@@ -29,6 +29,30 @@ namespace {
 // canonicalisation and the multiplication by 2^scale_e.
 // ---------------------------------------------------------------------------
 
+// Four columns of the MAC loop: acc[c] += aw[c] bj (64-bit, the carry out of
+// each multiply-add into its own SGPR pair), then cy[c] += that carry.  Two
+// instructions per limb product; written as instructions because the compiler
+// otherwise rebuilds the 64-bit sum with compares and selects.  The four
+// multiply-adds come first, so three instructions separate each carry write
+// from its read (the VALU SGPR-write to carry-read hazard needs two).
+// Registers only (no memory access).
+template <int C0, int NC>
+__device__ __forceinline__ void mac4(uint64_t (&acc)[NC], uint32_t (&cy)[NC], const uint32_t (&aw)[NC], uint32_t bj) {
+    uint64_t c0, c1, c2, c3;
+    asm("v_mad_u64_u32 %0, %4, %8, %12, %0\n\t"
+        "v_mad_u64_u32 %1, %5, %9, %12, %1\n\t"
+        "v_mad_u64_u32 %2, %6, %10, %12, %2\n\t"
+        "v_mad_u64_u32 %3, %7, %11, %12, %3"
+        : "+v"(acc[C0]), "+v"(acc[C0 + 1]), "+v"(acc[C0 + 2]), "+v"(acc[C0 + 3]), "=&s"(c0), "=&s"(c1), "=&s"(c2),
+          "=&s"(c3)
+        : "v"(aw[C0]), "v"(aw[C0 + 1]), "v"(aw[C0 + 2]), "v"(aw[C0 + 3]), "v"(bj));
+    asm("v_addc_co_u32_e64 %0, %4, %0, 0, %4\n\t"
+        "v_addc_co_u32_e64 %1, %5, %1, 0, %5\n\t"
+        "v_addc_co_u32_e64 %2, %6, %2, 0, %6\n\t"
+        "v_addc_co_u32_e64 %3, %7, %3, 0, %7"
+        : "+v"(cy[C0]), "+v"(cy[C0 + 1]), "+v"(cy[C0 + 2]), "+v"(cy[C0 + 3]), "+s"(c0), "+s"(c1), "+s"(c2), "+s"(c3));
+}
+
 // threads of a pointwise workgroup for W limbs (64..256) and columns per thread
 constexpr uint32_t pw_threads(int W) {
     uint32_t t = (uint32_t)W / 8u;
@@ -102,20 +126,44 @@ __device__ __forceinline__ void pointwise_body(const uint32_t *a, uint32_t ta, c
                 aw[cc] = A[k0 + cc];  // window at j = 0: A2[k0 + cc]
                 Tk[cc] = (uint64_t)P1[k0 + cc] << 32 | P0[k0 + cc];
             }
-            // unrolled by the window width so that the slide below is register renaming
-#pragma unroll NC
-            for (uint32_t j = 0; j < (uint32_t)W; ++j) {
-                const uint64_t bj = Bv[j];
+            if constexpr (NC % 4 == 0) {
+                // S_k = acc + 2^64 cy: 64-bit sums of the products and a count of their wraps
+                uint64_t acc[NC];
+                uint32_t cy[NC];
 #pragma unroll
                 for (int cc = 0; cc < NC; ++cc) {
-                    const uint64_t t = aw[cc] * bj + lo[cc];
-                    lo[cc] = (uint32_t)t;
-                    hi[cc] += t >> 32;
+                    acc[cc] = 0;
+                    cy[cc] = 0;
                 }
-                // slide: the next j needs A2[(k0 + cc - j - 1) mod 2W]
+#pragma unroll NC
+                for (uint32_t j = 0; j < (uint32_t)W; ++j) {
+                    const uint32_t bj = Bv[j];
+                    static_for<0, NC / 4>([&](auto qc) { mac4<4 * decltype(qc)::value, NC>(acc, cy, aw, bj); });
 #pragma unroll
-                for (int cc = NC - 1; cc > 0; --cc) aw[cc] = aw[cc - 1];
-                aw[0] = A[(k0 - j - 1u) & (2u * W - 1u)];
+                    for (int cc = NC - 1; cc > 0; --cc) aw[cc] = aw[cc - 1];
+                    aw[0] = A[(k0 - j - 1u) & (2u * W - 1u)];
+                }
+#pragma unroll
+                for (int cc = 0; cc < NC; ++cc) {
+                    lo[cc] = (uint32_t)acc[cc];
+                    hi[cc] = (acc[cc] >> 32) + ((uint64_t)cy[cc] << 32);
+                }
+            } else {
+                // unrolled by the window width so that the slide below is register renaming
+#pragma unroll NC
+                for (uint32_t j = 0; j < (uint32_t)W; ++j) {
+                    const uint64_t bj = Bv[j];
+#pragma unroll
+                    for (int cc = 0; cc < NC; ++cc) {
+                        const uint64_t t = aw[cc] * bj + lo[cc];
+                        lo[cc] = (uint32_t)t;
+                        hi[cc] += t >> 32;
+                    }
+                    // slide: the next j needs A2[(k0 + cc - j - 1) mod 2W]
+#pragma unroll
+                    for (int cc = NC - 1; cc > 0; --cc) aw[cc] = aw[cc - 1];
+                    aw[0] = A[(k0 - j - 1u) & (2u * W - 1u)];
+                }
             }
         }
         __syncthreads();  // every thread has read its T_k out of P0/P1
