@@ -124,6 +124,16 @@ def _progress(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def _leg(fn):
+    """fn(), or {"error": message} if it raises (traceback on stderr)."""
+    import traceback
+    try:
+        return fn()
+    except Exception as e:  # noqa: BLE001 - reported in the output line
+        traceback.print_exc()
+        return {"error": "%s: %s" % (type(e).__name__, str(e)[:400])}
+
+
 def batch_leg(T, torch, count=4096, train_count=32, heldout=16, replays=3, k1_stride=16):
     """Many Z[x] products of uneven lengths: batched plan (cost-model parameters,
     hipGraph replay) against one-at-a-time zx_mul_ss with the default rule;
@@ -391,10 +401,12 @@ def main():
     }
     del out, ws, dg, dh
     torch.cuda.empty_cache()
+    # a failing secondary leg is reported in the line (with its traceback on
+    # stderr) instead of taking the measured headline with it
     _progress("other products")
-    line["other_products"] = other_products(T, torch)
+    line["other_products"] = _leg(lambda: other_products(T, torch))
     if not args.no_batch:
-        line["batch"] = batch_leg(T, torch)
+        line["batch"] = _leg(lambda: batch_leg(T, torch))
     if not args.no_cpu_baseline:
         _progress("cpu baseline (oracle sample)")
         line["cpu_baseline"] = cpu_baseline(g, N, l, len_g, n, alg_bytes)
