@@ -63,7 +63,7 @@ def alg_cells_itft(l, z, n, f):
     return cells
 
 
-def cpu_baseline(g_limbs_arr, N, l, z, n, alg_bytes, budget_s=15.0):
+def cpu_baseline(g_limbs_arr, N, l, z, n, alg_bytes, budget_s=12.0):
     """The oracle (eq. (1) evaluated directly, plain C) on a bounded sample, extrapolated."""
     import numpy as np
     from oracle import coracle
@@ -73,11 +73,13 @@ def cpu_baseline(g_limbs_arr, N, l, z, n, alg_bytes, budget_s=15.0):
     a = np.zeros((z, W), dtype=np.uint32)
     a[:, : g_limbs_arr.shape[1]] = g_limbs_arr[:z]
     tops = np.zeros(z, dtype=np.uint32)
-    # one probe output to size the sample, then a batch of outputs on all threads
+    # one probe output to size the sample (about budget_s seconds on all threads),
+    # then a batch of outputs on all threads
     t0 = time.perf_counter()
     coracle.fermat_dft_sampled(N, L, 0, a, tops, [1], nthreads=1)
     t_one = time.perf_counter() - t0
-    k = max(threads, min(4 * threads, int(budget_s * threads / max(t_one, 1e-6))))
+    k = max(threads, min(64 * threads, int(budget_s * threads / max(t_one, 1e-6))))
+    k -= k % threads
     js = [(7919 * i) % n for i in range(k)]
     t0 = time.perf_counter()
     coracle.fermat_dft_sampled(N, L, 0, a, tops, js, nthreads=threads)
