@@ -471,7 +471,9 @@ hipError_t launch_fermat_pointwise_items(uint32_t W, uint64_t nitems, uint32_t *
 hipError_t launch_fermat_pack(uint32_t W, const PackDesc *descs, uint32_t ndesc, const PackDesc &inl, uint64_t max_z,
                               uint32_t *x, uint64_t cap, bool transposed, hipStream_t st) {
     if (ndesc == 0 || max_z == 0) return hipSuccess;
-    uint64_t blocks = (max_z * W + 255) / 256;
+    // about 8 words per thread for the largest operand: with one grid row per
+    // descriptor, rows of small operands would otherwise launch mostly idle blocks
+    uint64_t blocks = (max_z * W + 2047) / 2048;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(fermat_pack_kernel, dim3((uint32_t)blocks, ndesc), dim3(256), 0, st, descs, inl, x, cap, W,
                        transposed ? 1u : 0u);
@@ -483,13 +485,14 @@ hipError_t launch_fermat_unpack(uint32_t W, const UnpackDesc *descs, uint32_t nd
                                 bool transposed, hipStream_t st) {
     if (ndesc == 0 || max_len == 0) return hipSuccess;
     const uint32_t tr = transposed ? 1u : 0u;
+    // about 8 words (coefficients) per thread (wave) for the largest product, as in the pack
     if (!bundled) {
-        uint64_t blocks = (max_len * max_olimbs + 255) / 256;
+        uint64_t blocks = (max_len * max_olimbs + 2047) / 2048;
         if (blocks > 4096) blocks = 4096;
         hipLaunchKernelGGL(fermat_unpack1_kernel, dim3((uint32_t)blocks, ndesc), dim3(256), 0, st, descs, inl, x, cap,
                            W, tr);
     } else {
-        uint64_t blocks = (max_len + 3) / 4;  // four waves per block, a wave per coefficient
+        uint64_t blocks = (max_len + 31) / 32;  // four waves per block, a wave per coefficient
         if (blocks > 4096) blocks = 4096;
         hipLaunchKernelGGL(fermat_unpackk_kernel, dim3((uint32_t)blocks, ndesc), dim3(256), 0, st, descs, inl, x, W,
                            tr);
