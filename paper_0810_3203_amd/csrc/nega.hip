@@ -7,6 +7,8 @@
 // y^K = -1; the ring needs no carries, so a coefficient is independent work.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "desc.hpp"
 #include "nega.hpp"
 
@@ -202,6 +204,39 @@ __device__ __forceinline__ void mul128(uint64_t a, uint64_t b, uint64_t &lo, uin
     hi = (uint64_t)a1 * b1 + (t1 >> 32) + (t2 >> 32);
 }
 
+template <int J, int N, class Fn>
+__device__ __forceinline__ void nega_static_for(Fn &&f) {
+    if constexpr (J < N) {
+        f(std::integral_constant<int, J>{});
+        nega_static_for<J + 1, N>(f);
+    }
+}
+
+// Four columns of products av * bw[c] (both < 2^63) added into column sums
+// kept as three accumulators per column: s0 = sum a0 b0 (+ 2^64 w0 wraps),
+// s1 = sum a0 b1 + a1 b0 (+ 2^64 w1 wraps), s2 = sum a1 b1 (no wrap within a
+// group), with a = a1 2^32 + a0.  Each wrapping sum takes a 64-bit multiply-add
+// with its carry-out into an SGPR pair and an add-with-carry into its count;
+// four multiply-adds precede their four carry reads (the VALU SGPR-write to
+// carry-read hazard needs two wait states).  Registers only (no memory access).
+template <int C0, int NC>
+__device__ __forceinline__ void nega_mac4(uint64_t (&acc)[NC], uint32_t (&w)[NC], uint32_t a,
+                                          const uint32_t (&b)[NC]) {
+    uint64_t c0, c1, c2, c3;
+    asm("v_mad_u64_u32 %0, %4, %8, %9, %0\n\t"
+        "v_mad_u64_u32 %1, %5, %8, %10, %1\n\t"
+        "v_mad_u64_u32 %2, %6, %8, %11, %2\n\t"
+        "v_mad_u64_u32 %3, %7, %8, %12, %3"
+        : "+v"(acc[C0]), "+v"(acc[C0 + 1]), "+v"(acc[C0 + 2]), "+v"(acc[C0 + 3]), "=&s"(c0), "=&s"(c1), "=&s"(c2),
+          "=&s"(c3)
+        : "v"(a), "v"(b[C0]), "v"(b[C0 + 1]), "v"(b[C0 + 2]), "v"(b[C0 + 3]));
+    asm("v_addc_co_u32_e64 %0, %4, %0, 0, %4\n\t"
+        "v_addc_co_u32_e64 %1, %5, %1, 0, %5\n\t"
+        "v_addc_co_u32_e64 %2, %6, %2, 0, %6\n\t"
+        "v_addc_co_u32_e64 %3, %7, %3, 0, %7"
+        : "+v"(w[C0]), "+v"(w[C0 + 1]), "+v"(w[C0 + 2]), "+v"(w[C0 + 3]), "+s"(c0), "+s"(c1), "+s"(c2), "+s"(c3));
+}
+
 // c_k = sum_i a_i b_{k-i} - sum_{i>k} a_i b_{k-i+K}  (mod m, y^K = -1), times 2^-scale.
 // Each thread owns NP_COLS consecutive columns and slides a register window
 // over B2 = [b, m - b] (the wrapped terms enter negated, so every product is
@@ -234,18 +269,53 @@ __global__ void __launch_bounds__(256) nega_pointwise_kernel(const uint64_t *__r
             lo[cc] = hi[cc] = r[cc] = 0;
             bw[cc] = B[k0 + cc];  // window at i = 0: B2[k0 + cc]
         }
+        // four-column blocks: partial products in three column accumulators
+        uint64_t s0[NC], s1[NC], s2[NC];
+        uint32_t w0[NC], w1[NC];
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) {
+            s0[cc] = s1[cc] = s2[cc] = 0;
+            w0[cc] = w1[cc] = 0;
+        }
         for (uint32_t ii = 0; ii < (uint32_t)K; ++ii) {
             const uint64_t av = A[ii];
+            if constexpr (NC % 4 == 0) {
+                const uint32_t a0 = (uint32_t)av, a1 = (uint32_t)(av >> 32);
+                uint32_t b0[NC], b1[NC];
 #pragma unroll
-            for (int cc = 0; cc < NC; ++cc) {
-                uint64_t pl, ph;
-                mul128(av, bw[cc], pl, ph);
-                lo[cc] += pl;
-                hi[cc] += ph + (lo[cc] < pl ? 1u : 0u);
+                for (int cc = 0; cc < NC; ++cc) {
+                    b0[cc] = (uint32_t)bw[cc];
+                    b1[cc] = (uint32_t)(bw[cc] >> 32);
+                }
+                nega_static_for<0, NC / 4>([&](auto qc) {
+                    constexpr int c4 = 4 * decltype(qc)::value;
+                    nega_mac4<c4, NC>(s0, w0, a0, b0);
+                    nega_mac4<c4, NC>(s1, w1, a0, b1);
+                    nega_mac4<c4, NC>(s1, w1, a1, b0);
+                });
+#pragma unroll
+                for (int cc = 0; cc < NC; ++cc) s2[cc] += (uint64_t)a1 * b1[cc];  // < 16 2^60, no wrap
+            } else {
+#pragma unroll
+                for (int cc = 0; cc < NC; ++cc) {
+                    uint64_t pl, ph;
+                    mul128(av, bw[cc], pl, ph);
+                    lo[cc] += pl;
+                    hi[cc] += ph + (lo[cc] < pl ? 1u : 0u);
+                }
             }
             if ((ii & (NP_GROUP - 1)) == NP_GROUP - 1 || ii + 1 == (uint32_t)K) {
 #pragma unroll
                 for (int cc = 0; cc < NC; ++cc) {
+                    if constexpr (NC % 4 == 0) {
+                        // sum = s0 + 2^64 w0 + 2^32 (s1 + 2^64 w1) + 2^64 s2
+                        const uint64_t t = s1[cc] << 32;
+                        lo[cc] = s0[cc] + t;
+                        hi[cc] = (uint64_t)w0[cc] + (s1[cc] >> 32) + ((uint64_t)w1[cc] << 32) + s2[cc] +
+                                 (lo[cc] < t ? 1u : 0u);
+                        s0[cc] = s1[cc] = s2[cc] = 0;
+                        w0[cc] = w1[cc] = 0;
+                    }
                     uint64_t h = hi[cc];  // < 16 m^2 / 2^64 < 4 m
                     h = h >= m2 ? h - m2 : h;
                     h = h >= m ? h - m : h;
