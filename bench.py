@@ -14,6 +14,7 @@ transforms, measured with HIP events on the stream the kernels run on.
 Inputs are resident in HBM before the timed region.  One JSON line is printed.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py --split-sweep     # cache-friendly vs divide-and-conquer transforms
 """
 
 import argparse
@@ -308,6 +309,66 @@ def other_products(T, torch, reps=5):
     return out
 
 
+def split_sweep(T, torch, bits=8000, lo=512, hi=16384, step=1.05, reps=3):
+    """Cache-friendly against divide-and-conquer transforms (Sect. 1, Sect. 5.1
+    experiment shape): Z[x] products of two random `bits`-bit polynomials of equal
+    length, lengths lo..hi in 5% steps, one coefficient per ring element.  Both
+    runs use the same ring, length and leaf size; the divide-and-conquer run
+    splits L1 = 2 at every level above the leaf.  Median of `reps` runs each;
+    the two outputs are compared bit for bit."""
+    import numpy as np
+    from synth import workloads as wl
+    from synth.splitmix import SplitMix64
+
+    limbs = bits // 32
+    lens, x = [], float(lo)
+    while round(x) <= hi:
+        lens.append(int(round(x)))
+        x *= step
+    rng = SplitMix64(0x0810320300000006)
+    rows = []
+    for ln in lens:
+        g, h = wl.random_ints(rng, ln, bits), wl.random_ints(rng, ln, bits)
+        dg = torch.from_numpy(g.view(np.int32)).cuda()
+        dh = torch.from_numpy(h.view(np.int32)).cuda()
+        ow = (32 * 2 * limbs + (ln - 1).bit_length() + 31) // 32
+        res = {}
+        outs = []
+        for name, top in (("bailey", 0), ("dc", T.SPLIT_DC)):
+            p = T.SSParams(0, 0, T.Split(top, 0), 1)
+            ws = torch.empty(T.zx_mul_ss_workspace(ln, limbs, ln, limbs, p), dtype=torch.uint8, device="cuda")
+            o = torch.empty((2 * ln - 1, ow), dtype=torch.int32, device="cuda")
+            T.zx_mul_ss_timed(dg, dh, o, p, ws=ws)
+            runs = sorted((T.zx_mul_ss_timed(dg, dh, o, p, ws=ws) for _ in range(reps)), key=lambda t: t["total_ms"])
+            t = runs[len(runs) // 2]
+            res[name] = t
+            outs.append(o)
+            del ws
+        same = bool(torch.equal(outs[0], outs[1]))
+        b, d = res["bailey"], res["dc"]
+
+        def tr(t):
+            return t["tft_g_ms"] + t["tft_h_ms"] + t["itft_ms"]
+
+        rows.append({"len": ln, "N": b["N"], "l": b["l"], "bailey_ms": round(b["total_ms"], 4),
+                     "dc_ms": round(d["total_ms"], 4), "bailey_transform_ms": round(tr(b), 4),
+                     "dc_transform_ms": round(tr(d), 4), "bailey_launches": b["leaf_launches"],
+                     "dc_launches": d["leaf_launches"], "same_output": same})
+        _progress("split sweep len %d: bailey %.3f ms, dc %.3f ms, same %s" % (ln, b["total_ms"], d["total_ms"], same))
+        del outs, dg, dh
+    gain = sorted(r["dc_ms"] / r["bailey_ms"] for r in rows)
+    tgain = sorted(r["dc_transform_ms"] / r["bailey_transform_ms"] for r in rows)
+    return {"experiment": "Z[x] products, %d-bit coefficients, lengths %d..%d in %d%% steps: "
+                          "cache-friendly (paper split) vs divide-and-conquer transforms" % (bits, lo, hi,
+                                                                                            round(100 * (step - 1))),
+            "rows": rows, "all_outputs_equal": all(r["same_output"] for r in rows),
+            "product_time_ratio_dc_over_bailey": {"min": round(gain[0], 3), "median": round(gain[len(gain) // 2], 3),
+                                                  "max": round(gain[-1], 3)},
+            "transform_time_ratio_dc_over_bailey": {"min": round(tgain[0], 3),
+                                                    "median": round(tgain[len(tgain) // 2], 3),
+                                                    "max": round(tgain[-1], 3)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -315,6 +376,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-products measurement")
+    ap.add_argument("--split-sweep", action="store_true",
+                    help="instead of the benchmark: cache-friendly vs divide-and-conquer transforms over a sweep "
+                         "of Z[x] products with 8000-bit coefficients (one JSON line)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run three plain 1 GiB device copies (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -330,6 +394,9 @@ def main():
     from synth import workloads as wl
 
     torch.cuda.set_device(0)
+    if args.split_sweep:
+        print(json.dumps(split_sweep(T, torch)), flush=True)
+        return
     spec = wl.ZX_CASES[3]
     g, h = wl.zx_operands(3)
     len_g, len_h = g.shape[0], h.shape[0]

@@ -70,7 +70,10 @@ typedef struct {
 } tft_ring;
 
 /* Split policy for the Bailey decomposition (Sect. 2: L = L1 L2).
- * top_l1     log2 of L1 at the top level; 0 = the paper's floor(l/2) (Alg. 1, Alg. 2).
+ * top_l1     log2 of L1 at the top level; 0 = the paper's floor(l/2) (Alg. 1, Alg. 2);
+ *            TFT_SPLIT_DC = L1 = 2 at every level above the leaf, i.e. van der
+ *            Hoeven's divide-and-conquer TFT/ITFT, the special case l1 = 1 that
+ *            the paper's introduction names as the order it improves on (Sect. 1).
  * leaf_log2  log2 of the largest sub-transform run inside one workgroup's LDS;
  *            0 = the largest that fits.  A larger value is accepted for planning
  *            (tft_plan_export) but tft_plan_execute then returns TFT_E_UNSUPPORTED.
@@ -79,6 +82,7 @@ typedef struct {
     uint32_t top_l1;
     uint32_t leaf_log2;
 } tft_split;
+#define TFT_SPLIT_DC 0xFFFFFFFFu
 
 /* Human-readable name of a status code (static string). */
 const char *tft_status_string(int status);

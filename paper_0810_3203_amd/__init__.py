@@ -10,6 +10,7 @@ from ._binding import (  # noqa: F401
     FERMAT,
     MLP,
     NEGA,
+    SPLIT_DC,
     SS_FEATURES,
     BatchPlan,
     Plan,
@@ -45,6 +46,6 @@ __all__ = [
     "FERMAT", "NEGA", "Plan", "SSParams", "Split", "TFTError", "array_bytes", "elem_bytes", "fermat_ring",
     "itft_inverse", "lib", "lib_path", "nega_ring", "pointwise_mul", "ring_check", "status_string", "tft_forward",
     "zmx_mul_nussbaumer", "zmx_mul_nussbaumer_workspace", "zx_mul_ss", "zx_mul_ss_timed", "zx_mul_ss_workspace",
-    "BatchPlan", "MLP", "SS_FEATURES", "ZXRequest", "requests_array", "ss_candidates", "ss_default_params",
+    "BatchPlan", "MLP", "SPLIT_DC", "SS_FEATURES", "ZXRequest", "requests_array", "ss_candidates", "ss_default_params",
     "ss_features", "ss_time", "zx_request",
 ]

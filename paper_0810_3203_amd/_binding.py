@@ -33,6 +33,10 @@ class Ring(ctypes.Structure):
         return "Ring((Z/%dZ)[y]/(y^%d+1))" % (self.m, self.K)
 
 
+# top_l1 value selecting L1 = 2 at every level above the leaf (TFT_SPLIT_DC)
+SPLIT_DC = 0xFFFFFFFF
+
+
 class Split(ctypes.Structure):
     _fields_ = [("top_l1", ctypes.c_uint32), ("leaf_log2", ctypes.c_uint32)]
 

@@ -18,6 +18,8 @@
 #include "plan.hpp"
 #include "ss.hpp"
 
+static_assert(tft::kSplitDC == TFT_SPLIT_DC, "divide-and-conquer split code");
+
 using namespace tft;
 
 struct tft_plan {
@@ -166,7 +168,8 @@ tft_plan *plan_build(const tft_ring *ring, uint32_t dir, uint32_t l, uint64_t s,
     // leaves exceed the LDS budget are refused when executed
     uint32_t leaf = max_leaf_log2(ring);
     if (split && split->leaf_log2) leaf = std::min<uint32_t>(11, split->leaf_log2);
-    uint32_t top = (split && split->top_l1 && split->top_l1 < l) ? split->top_l1 : 0;
+    uint32_t top = 0;
+    if (split && split->top_l1 && (split->top_l1 == kSplitDC || split->top_l1 < l)) top = split->top_l1;
     p->sched = build_schedule(dir, l, ring_ord(ring), p->s, z, n, p->f, leaf, top);
     const uint32_t seg = ring->kind == TFT_RING_FERMAT ? std::min<uint32_t>(ring->N / 32, 64) : 64;
     const uint32_t G = 64 / seg;
@@ -302,7 +305,7 @@ int tft_plan_create(const tft_ring *ring, uint32_t direction, uint32_t l, uint64
     if (!plan || direction > 1) return TFT_E_ARG;
     int st = check_transform_args(ring, direction, l, z, n, f);
     if (st) return st;
-    if (split && split->top_l1 && split->top_l1 >= l) return TFT_E_ARG;
+    if (split && split->top_l1 && split->top_l1 != TFT_SPLIT_DC && split->top_l1 >= l) return TFT_E_ARG;
     *plan = plan_build(ring, direction, l, s, z, n, f, split);
     return TFT_OK;
 }

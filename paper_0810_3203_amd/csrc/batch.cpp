@@ -187,7 +187,9 @@ int tft_batch_plan_create(const tft_zx_request *reqs, uint32_t count, uint64_t m
         int st = (!r.g || !r.h || !r.out) ? TFT_E_ARG
                                           : ss_shape(r.len_g, r.g_limbs, r.len_h, r.h_limbs, &r.params, &shapes[i]);
         if (!st && 32ull * r.out_limbs < shapes[i].bits) st = TFT_E_RANGE;
-        if (!st && r.params.split.top_l1 && r.params.split.top_l1 >= shapes[i].l) st = TFT_E_ARG;
+        if (!st && r.params.split.top_l1 && r.params.split.top_l1 != TFT_SPLIT_DC &&
+            r.params.split.top_l1 >= shapes[i].l)
+            st = TFT_E_ARG;
         if (!st && max_workspace && ((shapes[i].bytes + 255) & ~255ull) > max_workspace) st = TFT_E_WORKSPACE;
         P->status[i] = st;
     }

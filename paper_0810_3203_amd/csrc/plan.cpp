@@ -167,6 +167,7 @@ struct Builder {
     }
 
     uint32_t split_l1(uint32_t lg, bool top) const {
+        if (top_l1 == kSplitDC) return 1;
         if (top && top_l1 && top_l1 < lg) return top_l1;
         return lg / 2;
     }

@@ -19,6 +19,8 @@
 
 namespace tft {
 
+constexpr uint32_t kSplitDC = 0xFFFFFFFFu;  // TFT_SPLIT_DC of the C interface
+
 struct PassDesc {
     uint32_t job_begin;
     uint32_t job_count;
@@ -45,7 +47,8 @@ struct Schedule {
 // Build the schedule of TFT(L, theta^s, z, n) (direction 0) or
 // ITFT(L, theta^s, z, n, f) (direction 1) on an array of L = 2^l cells.
 // ord = order of theta; leaf_log2 = largest leaf (>= 1); top_l1 = 0 for the
-// paper's split.  Arguments must already be valid.
+// paper's split, kSplitDC for L1 = 2 at every level above the leaf (van der
+// Hoeven's divide-and-conquer order).  Arguments must already be valid.
 Schedule build_schedule(uint32_t direction, uint32_t l, uint32_t ord, uint64_t s, uint64_t z, uint64_t n, uint32_t f,
                         uint32_t leaf_log2, uint32_t top_l1);
 

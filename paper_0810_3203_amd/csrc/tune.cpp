@@ -102,9 +102,12 @@ int tft_ss_features(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h
     int st = ss_shape(len_g, g_limbs, len_h, h_limbs, p, &sh);
     if (st) return st;
     const uint32_t lm = leaf_max(sh.W);
-    const uint32_t top = (p && p->split.top_l1) ? p->split.top_l1 : sh.l / 2;
+    const bool dc = p && p->split.top_l1 == TFT_SPLIT_DC;
+    const uint32_t top = dc ? 1 : (p && p->split.top_l1) ? p->split.top_l1 : sh.l / 2;
     const double L = (double)sh.L, W = (double)sh.W;
-    const double passes = sh.l <= lm ? 1.0 : std::ceil((double)top / lm) + std::ceil((double)(sh.l - top) / lm);
+    const double passes = sh.l <= lm ? 1.0
+                          : dc       ? (double)(sh.l - lm + 1)
+                                     : std::ceil((double)top / lm) + std::ceil((double)(sh.l - top) / lm);
     float f[TFT_SS_FEATURES] = {
         log2f_safe((double)len_g) / 16.0f,
         log2f_safe((double)len_h) / 16.0f,

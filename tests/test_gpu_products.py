@@ -77,6 +77,17 @@ def test_zx_explicit_ring_and_splits(coracle):
         _check_sampled(coracle, g, h, got, ow, range(129))
 
 
+def test_zx_divide_and_conquer_split(coracle):
+    """L1 = 2 at every level above the leaf gives the same product (Sect. 1)."""
+    from synth.splitmix import SplitMix64
+    s = SplitMix64(78)
+    g, h = wl.random_ints(s, 700, 250), wl.random_ints(s, 450, 250)
+    for N, l, leaf in [(0, 0, 0), (1024, 11, 3), (2048, 11, 1)]:
+        note("zx_mul_ss divide-and-conquer split N=%d l=%d leaf=%d" % (N, l, leaf))
+        got, ow = _zx_gpu(g, h, T.SSParams(N, l, T.Split(T.SPLIT_DC, leaf)))
+        _check_sampled(coracle, g, h, got, ow, range(1149))
+
+
 def test_zx_case1_full(coracle):
     g, h = wl.zx_operands(1)
     note("zx_mul_ss case 1 (500 x 500, 64-bit)")

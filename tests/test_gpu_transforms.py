@@ -122,13 +122,44 @@ def test_itft_multipass(N, leaf):
             _run_itft(N, l, rng.randrange(2 * N), z, n, f, seed=z + n, leaf_log2=leaf)
 
 
+LARGE_RINGS = [16384, 32768, 131072]  # 512, 1024 and 4096 limbs a cell
+
+
+@pytest.mark.parametrize("N", LARGE_RINGS)
+def test_tft_large_rings(N):
+    rng = random.Random(N + 11)
+    for l, leaf in ((3, 0), (5, 0), (5, 2)):
+        L = 1 << l
+        for z, n in {(L, L), (1, L), (rng.randint(2, L), rng.randint(1, L))}:
+            _run_tft(N, l, rng.randrange(2 * N), z, n, seed=N + z + 5 * n, leaf_log2=leaf)
+
+
+@pytest.mark.parametrize("N", LARGE_RINGS)
+def test_itft_large_rings(N):
+    rng = random.Random(N + 12)
+    for l, leaf in ((3, 0), (5, 0), (5, 2)):
+        L = 1 << l
+        for z, n, f in {(L, L, 0), (L, L - 1, 1), (L - 3, rng.randint(1, L - 4), 1)}:
+            _run_itft(N, l, rng.randrange(2 * N), z, n, f, seed=N + z + 3 * n, leaf_log2=leaf)
+
+
+def test_divide_and_conquer_split_on_gpu():
+    rng = random.Random(91)
+    for N, l, leaf in ((512, 6, 2), (512, 8, 3), (8192, 7, 1)):
+        L = 1 << l
+        for z, n in {(L, L), (L // 2 + 3, L - 5), (rng.randint(1, L), rng.randint(1, L))}:
+            _run_tft(N, l, rng.randrange(2 * N), z, n, seed=z + n, top_l1=T.SPLIT_DC, leaf_log2=leaf)
+        for z, n, f in {(L, L, 0), (L - 3, L - 7, 1), (L // 2, L // 4 + 1, 0)}:
+            _run_itft(N, l, rng.randrange(2 * N), z, n, f, seed=z + n, top_l1=T.SPLIT_DC, leaf_log2=leaf)
+
+
 def test_every_top_split_on_gpu():
     for top in (1, 2, 3, 4, 5):
         _run_tft(512, 6, 77, 40, 61, seed=top, top_l1=top, leaf_log2=2)
         _run_itft(512, 6, 77, 50, 43, 1, seed=top, top_l1=top, leaf_log2=2)
 
 
-@pytest.mark.parametrize("N", [32, 64, 512, 4096, 65536])
+@pytest.mark.parametrize("N", [32, 64, 512, 4096, 16384, 65536, 131072])
 def test_pointwise(N):
     ring = O.FermatRing(N)
     rng = random.Random(N)
@@ -190,6 +221,32 @@ def test_nega_transforms(K):
             note("nega itft K=%d l=%d z=%d n=%d f=%d s=%d" % (K, l, z, n, f, s))
             x = nega_to_device(list(inputs) + _nega_inputs(ring, L - z, rng), K, L, torch)
             T.Plan(T.nega_ring(K, m), 1, l, s, z, n, f, 0, leaf).execute(x)
+            torch.cuda.synchronize()
+            assert nega_from_device(x, K, n + f) == expect
+
+
+def test_nega_divide_and_conquer_split():
+    K = 64
+    rng = random.Random(641)
+    m = (rng.getrandbits(62) | (1 << 61) | 1) & ((1 << 62) - 1)
+    ring = O.NegaRing(K, m)
+    for l, leaf in [(5, 2), (7, 1)]:
+        L = 1 << l
+        for z, n in {(L, L), (L - 5, L // 2 + 1)}:
+            a = _nega_inputs(ring, L, rng)
+            s = rng.randrange(2 * K)
+            note("nega tft divide-and-conquer K=%d l=%d z=%d n=%d s=%d leaf=%d" % (K, l, z, n, s, leaf))
+            x = nega_to_device(a, K, L, torch)
+            T.Plan(T.nega_ring(K, m), 0, l, s, z, n, 0, T.SPLIT_DC, leaf).execute(x)
+            torch.cuda.synchronize()
+            assert nega_from_device(x, K, n) == O.tft(ring, L, s, z, n, a[:z])
+        for z, n, f in {(L, L, 0), (L - 2, L - 9, 1)}:
+            a = _nega_inputs(ring, z, rng)
+            s = rng.randrange(2 * K)
+            inputs, expect = O.itft_case(ring, L, s, z, n, f, a)
+            note("nega itft divide-and-conquer K=%d l=%d z=%d n=%d f=%d s=%d leaf=%d" % (K, l, z, n, f, s, leaf))
+            x = nega_to_device(list(inputs) + _nega_inputs(ring, L - z, rng), K, L, torch)
+            T.Plan(T.nega_ring(K, m), 1, l, s, z, n, f, T.SPLIT_DC, leaf).execute(x)
             torch.cuda.synchronize()
             assert nega_from_device(x, K, n + f) == expect
 

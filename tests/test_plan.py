@@ -103,6 +103,44 @@ def test_every_top_split_gives_the_same_outputs(top_l1):
         _check_itft(FERMAT, l, rng.randrange(128), zi, ni, f, top_l1, 2, seed=zi + 100 * ni)
 
 
+@pytest.mark.parametrize("leaf_log2", [1, 2, 3])
+def test_divide_and_conquer_split_gives_the_same_outputs(leaf_log2):
+    """L1 = 2 at every level above the leaf (van der Hoeven's order, Sect. 1)."""
+    rng = random.Random(40 + leaf_log2)
+    for ring, ordv in ((FERMAT, 128), (NEGA, 32)):
+        for l in (2, 4, 5):
+            L = 1 << l
+            for _ in range(4):
+                z, n = rng.randint(1, L), rng.randint(1, L)
+                _check_tft(ring, l, rng.randrange(ordv), z, n, T.SPLIT_DC, leaf_log2, seed=z + 31 * n)
+                zi = rng.randint(1, L)
+                ni = rng.randint(0, zi)
+                f = 1 if ni == 0 else (0 if ni == L else rng.randint(0, 1))
+                _check_itft(ring, l, rng.randrange(ordv), zi, ni, f, T.SPLIT_DC, leaf_log2, seed=zi + 31 * ni)
+
+
+def test_divide_and_conquer_matches_the_leaf_recursion():
+    """A leaf runs the same L1 = 2 recursion inside LDS, so the divide-and-conquer
+    plan with leaves of length 2 performs exactly the base cases of one leaf
+    holding the whole transform; its TFT takes l - leaf + 1 passes."""
+    rng = random.Random(77)
+    ring = T.fermat_ring(2048)  # ord 4096
+    for l in range(2, 12):
+        L = 1 << l
+        for _ in range(4):
+            z, n = rng.randint(1, L), rng.randint(1, L)
+            dc = T.Plan(ring, 0, l, 0, z, n, 0, T.SPLIT_DC, 1)
+            assert dc.base_cases == T.Plan(ring, 0, l, 0, z, n, 0, 0, l).base_cases, (l, z, n)
+            zi = rng.randint(1, L)
+            ni = rng.randint(0, zi)
+            f = 1 if ni == 0 else (0 if ni == L else rng.randint(0, 1))
+            dci = T.Plan(ring, 1, l, 0, zi, ni, f, T.SPLIT_DC, 1)
+            assert dci.base_cases == T.Plan(ring, 1, l, 0, zi, ni, f, 0, l).base_cases, (l, zi, ni, f)
+        for leaf in (1, 3):
+            if l > leaf:
+                assert len(T.Plan(ring, 0, l, 0, L, L, 0, T.SPLIT_DC, leaf).export()["passes"]) == l - leaf + 1
+
+
 def test_nega_ring_schedules():
     rng = random.Random(5)
     for l in (1, 3, 5):
