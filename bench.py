@@ -309,13 +309,34 @@ def other_products(T, torch, reps=5):
     return out
 
 
+def padded_leg(T, torch, dg, dh, out, l, n, reps=3):
+    """The same product with n rounded up to whole rows of the paper split
+    (Sect. 6 zero-padding: no partial last row in the ITFT); the output must
+    equal the unpadded one bit for bit."""
+    p = T.SSParams(0, 0, T.Split(0, 0), 1, 1)
+    L2 = 1 << (l - l // 2)
+    ws = torch.empty(T.zx_mul_ss_workspace(dg.shape[0], dg.shape[1], dh.shape[0], dh.shape[1], p),
+                     dtype=torch.uint8, device="cuda")
+    o = torch.empty_like(out)
+    T.zx_mul_ss_timed(dg, dh, o, p, ws=ws)
+    runs = sorted((T.zx_mul_ss_timed(dg, dh, o, p, ws=ws) for _ in range(reps)), key=lambda t: t["total_ms"])
+    t = runs[len(runs) // 2]
+    same = bool(torch.equal(o, out))
+    del ws, o
+    return {"n_padded": -(-n // L2) * L2, "total_ms": round(t["total_ms"], 3),
+            "transform_ms": round(t["tft_g_ms"] + t["tft_h_ms"] + t["itft_ms"], 3), "itft_ms": round(t["itft_ms"], 3),
+            "pointwise_ms": round(t["pointwise_ms"], 3), "leaf_launches": t["leaf_launches"],
+            "same_output_as_unpadded": same}
+
+
 def split_sweep(T, torch, bits=8000, lo=512, hi=16384, step=1.05, reps=3):
     """Cache-friendly against divide-and-conquer transforms (Sect. 1, Sect. 5.1
     experiment shape): Z[x] products of two random `bits`-bit polynomials of equal
-    length, lengths lo..hi in 5% steps, one coefficient per ring element.  Both
+    length, lengths lo..hi in 5% steps, one coefficient per ring element.  All
     runs use the same ring, length and leaf size; the divide-and-conquer run
-    splits L1 = 2 at every level above the leaf.  Median of `reps` runs each;
-    the two outputs are compared bit for bit."""
+    splits L1 = 2 at every level above the leaf, and a third run pads n to whole
+    rows of the paper split (Sect. 6).  Median of `reps` runs each; the outputs
+    are compared bit for bit."""
     import numpy as np
     from synth import workloads as wl
     from synth.splitmix import SplitMix64
@@ -334,8 +355,8 @@ def split_sweep(T, torch, bits=8000, lo=512, hi=16384, step=1.05, reps=3):
         ow = (32 * 2 * limbs + (ln - 1).bit_length() + 31) // 32
         res = {}
         outs = []
-        for name, top in (("bailey", 0), ("dc", T.SPLIT_DC)):
-            p = T.SSParams(0, 0, T.Split(top, 0), 1)
+        for name, top, pad in (("bailey", 0, 0), ("dc", T.SPLIT_DC, 0), ("padded", 0, 1)):
+            p = T.SSParams(0, 0, T.Split(top, 0), 1, pad)
             ws = torch.empty(T.zx_mul_ss_workspace(ln, limbs, ln, limbs, p), dtype=torch.uint8, device="cuda")
             o = torch.empty((2 * ln - 1, ow), dtype=torch.int32, device="cuda")
             T.zx_mul_ss_timed(dg, dh, o, p, ws=ws)
@@ -344,8 +365,8 @@ def split_sweep(T, torch, bits=8000, lo=512, hi=16384, step=1.05, reps=3):
             res[name] = t
             outs.append(o)
             del ws
-        same = bool(torch.equal(outs[0], outs[1]))
-        b, d = res["bailey"], res["dc"]
+        same = bool(torch.equal(outs[0], outs[1])) and bool(torch.equal(outs[0], outs[2]))
+        b, d, w = res["bailey"], res["dc"], res["padded"]
 
         def tr(t):
             return t["tft_g_ms"] + t["tft_h_ms"] + t["itft_ms"]
@@ -353,20 +374,26 @@ def split_sweep(T, torch, bits=8000, lo=512, hi=16384, step=1.05, reps=3):
         rows.append({"len": ln, "N": b["N"], "l": b["l"], "bailey_ms": round(b["total_ms"], 4),
                      "dc_ms": round(d["total_ms"], 4), "bailey_transform_ms": round(tr(b), 4),
                      "dc_transform_ms": round(tr(d), 4), "bailey_launches": b["leaf_launches"],
-                     "dc_launches": d["leaf_launches"], "same_output": same})
-        _progress("split sweep len %d: bailey %.3f ms, dc %.3f ms, same %s" % (ln, b["total_ms"], d["total_ms"], same))
+                     "dc_launches": d["leaf_launches"], "padded_ms": round(w["total_ms"], 4),
+                     "padded_transform_ms": round(tr(w), 4), "padded_launches": w["leaf_launches"],
+                     "same_output": same})
+        _progress("split sweep len %d: bailey %.3f ms, dc %.3f ms, padded %.3f ms, same %s"
+                  % (ln, b["total_ms"], d["total_ms"], w["total_ms"], same))
         del outs, dg, dh
-    gain = sorted(r["dc_ms"] / r["bailey_ms"] for r in rows)
-    tgain = sorted(r["dc_transform_ms"] / r["bailey_transform_ms"] for r in rows)
+
+    def spread(key, ref):
+        v = sorted(r[key] / r[ref] for r in rows)
+        return {"min": round(v[0], 3), "median": round(v[len(v) // 2], 3), "max": round(v[-1], 3)}
+
     return {"experiment": "Z[x] products, %d-bit coefficients, lengths %d..%d in %d%% steps: "
-                          "cache-friendly (paper split) vs divide-and-conquer transforms" % (bits, lo, hi,
+                          "cache-friendly (paper split) vs divide-and-conquer transforms vs "
+                          "whole-row padding" % (bits, lo, hi,
                                                                                             round(100 * (step - 1))),
             "rows": rows, "all_outputs_equal": all(r["same_output"] for r in rows),
-            "product_time_ratio_dc_over_bailey": {"min": round(gain[0], 3), "median": round(gain[len(gain) // 2], 3),
-                                                  "max": round(gain[-1], 3)},
-            "transform_time_ratio_dc_over_bailey": {"min": round(tgain[0], 3),
-                                                    "median": round(tgain[len(tgain) // 2], 3),
-                                                    "max": round(tgain[-1], 3)}}
+            "product_time_ratio_dc_over_bailey": spread("dc_ms", "bailey_ms"),
+            "transform_time_ratio_dc_over_bailey": spread("dc_transform_ms", "bailey_transform_ms"),
+            "product_time_ratio_padded_over_bailey": spread("padded_ms", "bailey_ms"),
+            "transform_time_ratio_padded_over_bailey": spread("padded_transform_ms", "bailey_transform_ms")}
 
 
 def main():
@@ -468,6 +495,7 @@ def main():
             "avg_launch_ms": round(leaf_ms / max(1, launches), 4),
         },
     }
+    line["whole_row_padding"] = _leg(lambda: padded_leg(T, torch, dg, dh, out, l, n, reps=3))
     del out, ws, dg, dh
     torch.cuda.empty_cache()
     # a failing secondary leg is reported in the line (with its traceback on

@@ -134,12 +134,19 @@ int pointwise_mul(const tft_ring *ring, uint64_t n, const void *a, const void *b
  *          coefficient e*k+j of an operand sits in slot j (ws limbs, ws = the output
  *          coefficient bound in limbs) of cell e; a product cell holds 2k-1 slots
  *          (N >= 32 (2k-1) ws) and an output coefficient is the sum of two
- *          overlapping slots.  Results are identical for every k. */
+ *          overlapping slots.  Results are identical for every k.
+ *   pad_rows  0: the transforms are truncated at n, the number of product cells.
+ *          1: n is rounded up to whole rows of the top split, n' = L2 ceil(n/L2)
+ *          with L2 = L/L1 (the zero-padding of Sect. 6): TFT(g), TFT(h) give n'
+ *          values, n' pointwise products, ITFT(L, 1, n', n', 0).  The ITFT then
+ *          has no partial last row.  Cells n..n'-1 of the product are zero, so
+ *          the result is identical. */
 typedef struct {
     uint32_t N;
     uint32_t l;
     tft_split split;
     uint32_t k;
+    uint32_t pad_rows;
 } tft_ss_params;
 
 /* Workspace bytes zx_mul_ss needs for these operand shapes and parameters. */

@@ -442,9 +442,9 @@ static int ss_run(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uin
                                          : std::min(fit, std::max<uint32_t>(1, (sh.l + 1) / 2));
     }
     const tft_split *split = &sp;
-    tft_plan *pg = cached_plan(&ring, 0, sh.l, 0, sh.zg, sh.n, 0, split);
-    tft_plan *ph = cached_plan(&ring, 0, sh.l, 0, sh.zh, sh.n, 0, split);
-    tft_plan *pi = cached_plan(&ring, 1, sh.l, 0, sh.n, sh.n, 0, split);
+    tft_plan *pg = cached_plan(&ring, 0, sh.l, 0, sh.zg, sh.nt, 0, split);
+    tft_plan *ph = cached_plan(&ring, 0, sh.l, 0, sh.zh, sh.nt, 0, split);
+    tft_plan *pi = cached_plan(&ring, 1, sh.l, 0, sh.nt, sh.nt, 0, split);
     hipEvent_t ev[7] = {};
     LaunchTimer lt;
     LaunchTimer *ltp = tm ? &lt : nullptr;
@@ -467,7 +467,7 @@ static int ss_run(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uin
     if (!st) st = plan_run(ph, B, hs, ltp, true);
     if (!st && (e = mark(3)) != hipSuccess) st = dev_fail(e, "event");
     if (!st) {
-        e = launch_fermat_pointwise(sh.W, sh.n, A, B, A, sh.L, (uint32_t)((2 * sh.N - sh.l) % (2 * sh.N)), true, hs);
+        e = launch_fermat_pointwise(sh.W, sh.nt, A, B, A, sh.L, (uint32_t)((2 * sh.N - sh.l) % (2 * sh.N)), true, hs);
         if (e == hipSuccess) e = mark(4);
         if (e != hipSuccess) st = dev_fail(e, "pointwise");
     }

@@ -239,9 +239,9 @@ int tft_batch_plan_create(const tft_zx_request *reqs, uint32_t count, uint64_t m
                 if (r.params.split.leaf_log2)
                     leaf = std::min(fermat_max_leaf_log2(G.W), std::max<uint32_t>(1, r.params.split.leaf_log2));
                 const uint32_t top = r.params.split.top_l1;
-                sg.push_back(&sched(0, s.l, s.zg, s.n, top, leaf));
-                sh.push_back(&sched(0, s.l, s.zh, s.n, top, leaf));
-                si.push_back(&sched(1, s.l, s.n, s.n, top, leaf));
+                sg.push_back(&sched(0, s.l, s.zg, s.nt, top, leaf));
+                sh.push_back(&sched(0, s.l, s.zh, s.nt, top, leaf));
+                si.push_back(&sched(1, s.l, s.nt, s.nt, top, leaf));
             }
             const uint32_t G64 = 64u / std::min<uint32_t>(G.W, 64u);
             auto merge = [&](std::vector<Pass> &out, const std::vector<std::vector<const std::pair<Schedule, uint32_t> *>> &lists,
@@ -280,7 +280,7 @@ int tft_batch_plan_create(const tft_zx_request *reqs, uint32_t count, uint64_t m
                 const SSShape &s = shapes[i];
                 const tft_zx_request &r = reqs[i];
                 const uint32_t e = (uint32_t)((2ull * s.N - s.l) % (2ull * s.N));
-                for (uint64_t c = 0; c < s.n; c++)
+                for (uint64_t c = 0; c < s.nt; c++)
                     G.items.push_back(make_uint4((uint32_t)(offA[q] + c), (uint32_t)(offB[q] + c), e, 0u));
                 G.packs.push_back({r.g, r.len_g, offA[q], s.zg, r.g_limbs, s.k, s.ws, 0});
                 G.packs.push_back({r.h, r.len_h, offB[q], s.zh, r.h_limbs, s.k, s.ws, 0});

@@ -13,6 +13,7 @@ namespace tft {
 struct SSShape {
     uint32_t N, W, l, k, ws;
     uint64_t zg, zh, n, L, bytes;
+    uint64_t nt;    // truncation of the transforms: n, or n rounded up to whole top-level rows
     uint64_t bits;  // bound on the bits of an output coefficient
 };
 
@@ -55,6 +56,15 @@ inline int ss_shape(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h
     o->zg = zg;
     o->zh = zh;
     o->n = n;
+    o->nt = n;
+    if (p && p->pad_rows) {
+        if (p->pad_rows > 1) return TFT_E_ARG;
+        // rows of the top split (Alg. 1, Alg. 2): L2 = 2^(l - l1)
+        const uint32_t t = p->split.top_l1;
+        const uint32_t l1 = t == TFT_SPLIT_DC ? 1u : (t && t < l) ? t : l / 2;
+        const uint64_t L2 = 1ull << (l - l1);
+        o->nt = (n + L2 - 1) / L2 * L2;
+    }
     o->L = L;
     o->bytes = 2 * L * (W + 1) * 4ull;
     o->bits = bits;

@@ -88,6 +88,19 @@ def test_zx_divide_and_conquer_split(coracle):
         _check_sampled(coracle, g, h, got, ow, range(1149))
 
 
+def test_zx_whole_row_padding(coracle):
+    """n rounded up to whole rows of the top split (Sect. 6) gives the same product."""
+    from synth.splitmix import SplitMix64
+    s = SplitMix64(79)
+    g, h = wl.random_ints(s, 611, 300), wl.random_ints(s, 390, 300)
+    for p in [T.SSParams(0, 0, T.Split(0, 0), 1, 1), T.SSParams(0, 0, T.Split(3, 0), 1, 1),
+              T.SSParams(0, 0, T.Split(T.SPLIT_DC, 2), 1, 1), T.SSParams(0, 0, T.Split(0, 0), 3, 1),
+              T.SSParams(32768, 11, T.Split(0, 2), 1, 1)]:
+        note("zx_mul_ss whole rows N=%d l=%d k=%d split %d/%d" % (p.N, p.l, p.k, p.split.top_l1, p.split.leaf_log2))
+        got, ow = _zx_gpu(g, h, p)
+        _check_sampled(coracle, g, h, got, ow, range(1000))
+
+
 def test_zx_case1_full(coracle):
     g, h = wl.zx_operands(1)
     note("zx_mul_ss case 1 (500 x 500, 64-bit)")

@@ -172,6 +172,42 @@ def test_polynomial_product_through_the_schedule():
     assert [ring.mul(v, ring.inv_pow2(l)) for v in u[:n]] == O.zx_mul(g, h)
 
 
+@pytest.mark.parametrize("top_l1", [0, 2, T.SPLIT_DC])
+def test_whole_row_padding_through_the_schedule(top_l1):
+    """Sect. 6 zero-padding: with n rounded up to whole rows of the top split the
+    same three transforms give L (g h) followed by zeros, and the ITFT plan has
+    no partial last row, so it needs fewer passes."""
+    ring = FERMAT
+    rng = random.Random(9 + (top_l1 & 7))
+    l, L = 6, 64
+    l1 = 1 if top_l1 == T.SPLIT_DC else (top_l1 or l // 2)
+    L2 = L >> l1
+    for lg, lh in ((21, 30), (5, 9), (17, 17)):
+        g = [rng.randrange(1 << 20) for _ in range(lg)]
+        h = [rng.randrange(1 << 20) for _ in range(lh)]
+        n = lg + lh - 1
+        npad = -(-n // L2) * L2
+        pg = T.Plan(_lib_ring(ring), 0, l, 0, lg, npad, 0, top_l1, 2).export()
+        ph = T.Plan(_lib_ring(ring), 0, l, 0, lh, npad, 0, top_l1, 2).export()
+        xg = simulate(pg, ring, g + [0] * (L - lg))
+        xh = simulate(ph, ring, h + [0] * (L - lh))
+        u = [ring.mul(a, b) for a, b in zip(xg[:npad], xh[:npad])] + [rng.randrange(ring.p) for _ in range(L - npad)]
+        pi = T.Plan(_lib_ring(ring), 1, l, 0, npad, npad, 0, top_l1, 2)
+        u = simulate(pi.export(), ring, u)
+        assert [ring.mul(v, ring.inv_pow2(l)) for v in u[:npad]] == O.zx_mul(g, h) + [0] * (npad - n)
+        if n % L2:
+            plain = T.Plan(_lib_ring(ring), 1, l, 0, n, n, 0, top_l1, 2).export()
+            assert len(pi.export()["passes"]) <= len(plain["passes"])
+
+
+def test_whole_row_padding_pass_counts_large_case():
+    """Z/(2^65536+1), L = 2^17, n = 99999: padding to 100352 = 196 rows of 512
+    takes the ITFT from 19 passes to 7 with leaves of 16 cells."""
+    ring = T.fermat_ring(65536)
+    assert len(T.Plan(ring, 1, 17, 0, 99999, 99999, 0, 0, 4).export()["passes"]) == 19
+    assert len(T.Plan(ring, 1, 17, 0, 100352, 100352, 0, 0, 4).export()["passes"]) == 7
+
+
 # ---------------------------------------------------------------------------
 # base-case counts (Theorems 1 and 2)
 # ---------------------------------------------------------------------------
