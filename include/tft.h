@@ -250,11 +250,13 @@ void tft_batch_plan_destroy(tft_batch_plan *plan);
  * product allows) and the top split of Alg. 1/2.  Every candidate gives the
  * same output bits; only the time differs. */
 
-#define TFT_SS_FEATURES 12
+#define TFT_SS_FEATURES 13
 
 /* The candidate set of a product shape, in a fixed order: k = 1, 2, 4, ..., 32
  * (those the ring sizes allow), each with the paper's split and, when the
- * transform needs more than one leaf, a split whose column pass is one leaf.
+ * transform needs more than one leaf, a split whose column pass is one leaf;
+ * each of these is followed by its whole-row padded form (pad_rows = 1) when
+ * padding changes the truncation.
  * out == NULL: only *count is set.  TFT_E_ARG if cap < *count. */
 int tft_ss_candidates(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h_limbs, tft_ss_params *out,
                       uint32_t cap, uint32_t *count);
@@ -267,7 +269,7 @@ int tft_ss_default_params(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint
 /* TFT_SS_FEATURES scaled features of (product shape, candidate) read by the
  * cost model: operand lengths and limbs, k, l, ring size, fill n/L,
  * footprint, pointwise limb products, transform pass bytes, pass count,
- * top split share.  Host work only. */
+ * top split share, padded cells.  Host work only. */
 int tft_ss_features(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h_limbs, const tft_ss_params *p,
                     float *feat);
 

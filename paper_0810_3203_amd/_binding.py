@@ -62,7 +62,7 @@ class ZXRequest(ctypes.Structure):
                 ("out", ctypes.c_void_p), ("out_limbs", ctypes.c_uint32), ("params", SSParams)]
 
 
-SS_FEATURES = 12
+SS_FEATURES = 13
 
 
 def fermat_ring(N: int) -> Ring:

@@ -27,20 +27,27 @@ uint32_t leaf_max(uint32_t W) {
 
 std::vector<tft_ss_params> candidates(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h_limbs) {
     std::vector<tft_ss_params> out;
+    // p, then p with n padded to whole rows when that changes the truncation
+    auto push = [&](tft_ss_params p) {
+        out.push_back(p);
+        p.pad_rows = 1;
+        SSShape sp;
+        if (!ss_shape(len_g, g_limbs, len_h, h_limbs, &p, &sp) && sp.nt != sp.n) out.push_back(p);
+    };
     for (uint32_t k : kKs) {
         tft_ss_params p{};
         p.k = k;
         SSShape sh;
         if (ss_shape(len_g, g_limbs, len_h, h_limbs, &p, &sh)) continue;
         if (sh.n < 2 && k > 1) continue;  // larger k cannot shrink a single-cell product
-        out.push_back(p);
+        push(p);
         // second split: one column pass of leaf size, then rows of the rest
         const uint32_t lm = leaf_max(sh.W);
         if (sh.l > lm) {
             const uint32_t top = sh.l - lm;
             if (top != sh.l / 2 && top >= 1) {
                 p.split.top_l1 = top;
-                out.push_back(p);
+                push(p);
             }
         }
         if (sh.n == 1) break;
@@ -121,6 +128,7 @@ int tft_ss_features(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h
         log2f_safe((double)sh.bytes * passes) / 36.0f,       // bytes moved by the transform passes
         (float)passes / 8.0f,
         (float)top / (float)sh.l,                             // share of the top split in the columns
+        (float)((double)(sh.nt - sh.n) / std::ldexp(1.0, (int)(sh.l - top))),  // padded share of a top row
     };
     std::copy(f, f + TFT_SS_FEATURES, feat);
     return TFT_OK;
