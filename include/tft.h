@@ -267,9 +267,10 @@ int tft_ss_default_params(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint
                           tft_ss_params *out);
 
 /* TFT_SS_FEATURES scaled features of (product shape, candidate) read by the
- * cost model: operand lengths and limbs, k, l, ring size, fill n/L,
- * footprint, pointwise limb products, transform pass bytes, pass count,
- * top split share, padded cells.  Host work only. */
+ * cost model: operand lengths and limbs, k, l, ring size, fill n/L (n the
+ * transforms' truncation, padded or not), footprint, pointwise limb products,
+ * transform pass bytes, leaf passes of a TFT, top split share, leaf passes of
+ * the ITFT.  Host work only. */
 int tft_ss_features(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h_limbs, const tft_ss_params *p,
                     float *feat);
 

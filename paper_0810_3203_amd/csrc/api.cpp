@@ -272,6 +272,13 @@ tft_plan *cached_plan(const tft_ring *ring, uint32_t dir, uint32_t l, uint64_t s
 
 namespace tft {
 int device_error(hipError_t e, const char *where) { return dev_fail(e, where); }
+
+uint32_t ss_leaf_log2(uint32_t N, uint32_t l) {
+    const tft_ring ring{TFT_RING_FERMAT, N, 0, 0, 0};
+    const uint32_t fit = max_leaf_log2(&ring), fill = fill_log2();
+    return (l > fill + 3) ? std::min(fit, std::max<uint32_t>(3, l - fill))
+                          : std::min(fit, std::max<uint32_t>(1, (l + 1) / 2));
+}
 }  // namespace tft
 
 extern "C" {
@@ -436,11 +443,7 @@ static int ss_run(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uin
     // a small transform takes two passes of half its length rather than one
     // workgroup running every level alone.
     tft_split sp = params ? params->split : tft_split{0, 0};
-    if (!sp.leaf_log2) {
-        const uint32_t fit = max_leaf_log2(&ring), fill = fill_log2();
-        sp.leaf_log2 = (sh.l > fill + 3) ? std::min(fit, std::max<uint32_t>(3, sh.l - fill))
-                                         : std::min(fit, std::max<uint32_t>(1, (sh.l + 1) / 2));
-    }
+    if (!sp.leaf_log2) sp.leaf_log2 = ss_leaf_log2(sh.N, sh.l);
     const tft_split *split = &sp;
     tft_plan *pg = cached_plan(&ring, 0, sh.l, 0, sh.zg, sh.nt, 0, split);
     tft_plan *ph = cached_plan(&ring, 0, sh.l, 0, sh.zh, sh.nt, 0, split);

@@ -231,7 +231,65 @@ struct Builder {
     }
 };
 
+// Pass counts of Alg. 1 / Alg. 2 plans: the recursion of Builder::plan_tft and
+// Builder::plan_itft with each phase's depth the largest over its sub-plans.
+struct PassCounter {
+    uint32_t leaf_log2, top_l1;
+    std::map<std::tuple<uint32_t, uint64_t, uint64_t, uint32_t, bool>, uint32_t> memo;
+
+    uint32_t l1_of(uint32_t lg, bool top) const {
+        if (top_l1 == kSplitDC) return 1;
+        if (top && top_l1 && top_l1 < lg) return top_l1;
+        return lg / 2;
+    }
+    uint32_t tft(uint32_t lg, uint64_t z, uint64_t n, bool top) {
+        if (lg <= leaf_log2) return 1;
+        auto key = std::make_tuple(lg, z, n, 0u, top);
+        auto it = memo.find(key);
+        if (it != memo.end()) return it->second;
+        const uint32_t l1 = l1_of(lg, top), l2 = lg - l1;
+        const uint64_t L2 = 1ull << l2;
+        const uint64_t n1 = n / L2, n2 = n % L2, n1p = (n + L2 - 1) / L2;
+        const uint64_t z1 = z / L2, z2 = z % L2, z2p = z1 ? L2 : z2;
+        uint32_t dc = 0, dr = 0;
+        if (z2) dc = std::max(dc, tft(l1, z1 + 1, n1p, false));  // columns u < z2
+        if (z2p > z2) dc = std::max(dc, tft(l1, z1, n1p, false));  // columns z2 <= u < z2p
+        if (n1) dr = std::max(dr, tft(l2, z2p, L2, false));
+        if (n2) dr = std::max(dr, tft(l2, z2p, n2, false));
+        return memo[key] = dc + dr;
+    }
+    uint32_t itft(uint32_t lg, uint64_t z, uint64_t n, uint32_t f, bool top) {
+        if (lg <= leaf_log2) return 1;
+        auto key = std::make_tuple(lg, z, n, f + 2u, top);
+        auto it = memo.find(key);
+        if (it != memo.end()) return it->second;
+        const uint32_t l1 = l1_of(lg, top), l2 = lg - l1;
+        const uint64_t L2 = 1ull << l2;
+        const uint64_t n1 = n / L2, n2 = n % L2, z1 = z / L2, z2 = z % L2;
+        const uint32_t fp = (n2 + f > 0) ? 1 : 0;
+        const uint64_t z2p = z1 ? L2 : z2;
+        const uint64_t m = std::min(n2, z2), mp = std::max(n2, z2);
+        uint32_t d = 0;
+        if (n1) d += itft(l2, L2, L2, 0, false);  // full rows
+        uint32_t dr = 0;                           // right columns n2 <= u < z2p
+        if (n2 < std::min(mp, z2p)) dr = std::max(dr, itft(l1, z1 + 1, n1, fp, false));
+        if (std::max(n2, mp) < z2p) dr = std::max(dr, itft(l1, z1, n1, fp, false));
+        d += dr;
+        if (fp) d += itft(l2, z2p, n2, f, false);  // last row
+        uint32_t dl = 0;                           // left columns u < n2
+        if (m) dl = std::max(dl, itft(l1, z1 + 1, n1 + 1, 0, false));
+        if (n2 > m) dl = std::max(dl, itft(l1, z1, n1 + 1, 0, false));
+        return memo[key] = d + dl;
+    }
+};
+
 }  // namespace
+
+uint32_t schedule_pass_count(uint32_t direction, uint32_t l, uint64_t z, uint64_t n, uint32_t f, uint32_t leaf_log2,
+                             uint32_t top_l1) {
+    PassCounter pc{leaf_log2 < 1 ? 1 : leaf_log2, top_l1, {}};
+    return direction == 0 ? pc.tft(l, z, n, true) : pc.itft(l, z, n, f, true);
+}
 
 Schedule build_schedule(uint32_t direction, uint32_t l, uint32_t ord, uint64_t s, uint64_t z, uint64_t n, uint32_t f,
                         uint32_t leaf_log2, uint32_t top_l1) {

@@ -52,4 +52,11 @@ struct Schedule {
 Schedule build_schedule(uint32_t direction, uint32_t l, uint32_t ord, uint64_t s, uint64_t z, uint64_t n, uint32_t f,
                         uint32_t leaf_log2, uint32_t top_l1);
 
+// Number of passes build_schedule gives for the same arguments, from the
+// recursion alone (no jobs are built): the column and row sub-plans of one
+// level that share a shape take the same passes, so only the distinct shapes
+// of each level are followed.
+uint32_t schedule_pass_count(uint32_t direction, uint32_t l, uint64_t z, uint64_t n, uint32_t f, uint32_t leaf_log2,
+                             uint32_t top_l1);
+
 }  // namespace tft

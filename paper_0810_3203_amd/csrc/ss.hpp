@@ -17,6 +17,11 @@ struct SSShape {
     uint64_t bits;  // bound on the bits of an output coefficient
 };
 
+// Leaf size (log2 cells) of one product's transforms when the caller leaves it
+// open: about two leaf jobs per compute unit per pass for long transforms, two
+// half-length passes for short ones, never beyond what fits the LDS.
+uint32_t ss_leaf_log2(uint32_t N, uint32_t l);
+
 inline uint32_t ss_log2u(uint64_t v) {
     uint32_t l = 0;
     while ((1ull << l) < v) l++;

@@ -10,6 +10,7 @@
 
 #include "../../include/tft.h"
 #include "kernels.hpp"
+#include "plan.hpp"
 #include "ss.hpp"
 
 using namespace tft;
@@ -108,13 +109,17 @@ int tft_ss_features(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h
     SSShape sh;
     int st = ss_shape(len_g, g_limbs, len_h, h_limbs, p, &sh);
     if (st) return st;
-    const uint32_t lm = leaf_max(sh.W);
     const bool dc = p && p->split.top_l1 == TFT_SPLIT_DC;
-    const uint32_t top = dc ? 1 : (p && p->split.top_l1) ? p->split.top_l1 : sh.l / 2;
+    const uint32_t top = dc ? 1 : (p && p->split.top_l1 && p->split.top_l1 < sh.l) ? p->split.top_l1 : sh.l / 2;
     const double L = (double)sh.L, W = (double)sh.W;
-    const double passes = sh.l <= lm ? 1.0
-                          : dc       ? (double)(sh.l - lm + 1)
-                                     : std::ceil((double)top / lm) + std::ceil((double)(sh.l - top) / lm);
+    // leaf passes of the three transforms as zx_mul_ss plans them
+    const uint32_t leaf = (p && p->split.leaf_log2) ? std::min(leaf_max(sh.W), p->split.leaf_log2)
+                                                    : ss_leaf_log2(sh.N, sh.l);
+    const uint32_t tsplit = p ? p->split.top_l1 : 0;
+    const uint32_t pt = std::max(schedule_pass_count(0, sh.l, sh.zg, sh.nt, 0, leaf, tsplit),
+                                 schedule_pass_count(0, sh.l, sh.zh, sh.nt, 0, leaf, tsplit));
+    const uint32_t pi = schedule_pass_count(1, sh.l, sh.nt, sh.nt, 0, leaf, tsplit);
+    const double passes = 2.0 * pt + pi;
     float f[TFT_SS_FEATURES] = {
         log2f_safe((double)len_g) / 16.0f,
         log2f_safe((double)len_h) / 16.0f,
@@ -122,13 +127,13 @@ int tft_ss_features(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h
         log2f_safe((double)sh.k) / 8.0f,
         (float)sh.l / 16.0f,
         log2f_safe(W) / 12.0f,
-        (float)((double)sh.n / L),
+        (float)((double)sh.nt / L),
         log2f_safe((double)sh.bytes) / 32.0f,
-        log2f_safe((double)sh.n * W * W) / 40.0f,            // schoolbook pointwise limb products
-        log2f_safe((double)sh.bytes * passes) / 36.0f,       // bytes moved by the transform passes
-        (float)passes / 8.0f,
+        log2f_safe((double)sh.nt * W * W) / 40.0f,           // schoolbook pointwise limb products
+        log2f_safe((double)sh.bytes * passes / 3.0) / 36.0f, // bytes moved by the transform passes
+        (float)pt / 8.0f,                                     // leaf passes of one TFT
         (float)top / (float)sh.l,                             // share of the top split in the columns
-        (float)((double)(sh.nt - sh.n) / std::ldexp(1.0, (int)(sh.l - top))),  // padded share of a top row
+        (float)pi / 32.0f,                                    // leaf passes of the ITFT
     };
     std::copy(f, f + TFT_SS_FEATURES, feat);
     return TFT_OK;

@@ -62,3 +62,23 @@ def test_bad_shapes_rejected():
         T.ss_candidates(0, 32, 10, 32)
     with pytest.raises(T.TFTError):
         T.ss_default_params(10, 0, 10, 32)
+
+
+@pytest.mark.parametrize("lg,lh,N,l,top,leaf,pad", [
+    (500, 500, 512, 10, 0, 2, 0), (500, 500, 512, 10, 0, 2, 1), (3000, 2999, 8192, 13, 0, 3, 0),
+    (3000, 2999, 8192, 13, 0, 3, 1), (700, 300, 2048, 11, 7, 2, 1), (700, 300, 2048, 11, T.SPLIT_DC, 3, 0),
+    (1, 1, 64, 1, 0, 1, 0), (5000, 4000, 16384, 14, 0, 4, 1)])
+def test_pass_count_features_match_the_planner(lg, lh, N, l, top, leaf, pad):
+    """Features 11 and 13 are the leaf passes of one TFT and of the ITFT, from the
+    planner's recursion without building jobs; they must equal the pass counts
+    of the schedules the planner builds."""
+    p = T.SSParams(N, l, T.Split(top, leaf), 1, pad)
+    f = T.ss_features(lg, 1, lh, 1, p)
+    n = lg + lh - 1
+    l1 = 1 if top == T.SPLIT_DC else (top if 0 < top < l else l // 2)
+    L2 = 1 << (l - l1)
+    nt = -(-n // L2) * L2 if pad else n
+    ring = T.fermat_ring(N)
+    pt = max(len(T.Plan(ring, 0, l, 0, z, nt, 0, top, leaf).export()["passes"]) for z in (lg, lh))
+    pi = len(T.Plan(ring, 1, l, 0, nt, nt, 0, top, leaf).export()["passes"])
+    assert round(f[10] * 8) == pt and round(f[12] * 32) == pi, (f[10] * 8, pt, f[12] * 32, pi)
