@@ -188,6 +188,7 @@ def batch_leg(T, torch, count=4096, train_count=32, heldout=16, replays=3, k1_st
     ks = {}
     for r in arr:
         ks[r.params.k] = ks.get(r.params.k, 0) + 1
+    padded = sum(1 for r in arr if r.params.pad_rows)
 
     t0 = time.perf_counter()
     plan = T.BatchPlan(arr, max_workspace=96 << 30)
@@ -261,6 +262,7 @@ def batch_leg(T, torch, count=4096, train_count=32, heldout=16, replays=3, k1_st
         "k1_sample": "every %dth request (%d), time scaled by %d/%d" % (k1_stride, len(sel), count, len(sel)),
         "bit_exact_vs_one_at_a_time": bool(exact and exact_k1),
         "k_chosen": {str(k): v for k, v in sorted(ks.items())},
+        "padded_chosen": padded,
         "cost_model": {"train_requests": train_count, "train_rows": len(X), "final_loss": round(loss, 5),
                        "heldout_requests": heldout, "heldout_regret": round(t_mlp / t_best - 1, 4),
                        "heldout_gain_vs_default": round(t_def / t_mlp, 4)},

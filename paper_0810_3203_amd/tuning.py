@@ -2,7 +2,8 @@
 
 Gathers exhaustive timings (tft_ss_time) of every candidate of a set of
 requests, turns them into training rows for the cost model (features from
-tft_ss_features, target = log of the median time in ms), and applies the
+tft_ss_features, target = log of the median time in ms relative to the
+request's other candidates), and applies the
 three selection policies: the fixed default rule, the exhaustive best per
 request, and the cost model's argmin.  The timing, training and inference all
 run in libtft.so; this module only loops and marshals.
@@ -32,12 +33,17 @@ def time_candidates(reqs, reps=3, device="cuda", stream=None):
 
 
 def training_rows(reqs, timings):
-    """Features (rows x SS_FEATURES) and targets log(ms) from time_candidates output."""
+    """Features (rows x SS_FEATURES) and targets from time_candidates output.  A
+    target is log(ms) less the mean log(ms) over the request's candidates: only
+    the order of one request's candidates decides the choice, so the model is
+    fitted to that and not to the size of the request."""
     X, y = [], []
     for r, (cands, ms, _) in zip(reqs, timings):
-        for c, t in zip(cands, ms):
+        logs = [math.log(max(t, 1e-4)) for t in ms]
+        mean = sum(logs) / len(logs)
+        for c, v in zip(cands, logs):
             X.append(B.ss_features(r.len_g, r.g_limbs, r.len_h, r.h_limbs, c))
-            y.append(math.log(max(t, 1e-4)))
+            y.append(v - mean)
     return X, y
 
 
@@ -53,7 +59,7 @@ def train_model(X, y, hidden=64, depth=3, iters=3000, lr=2e-3, seed=11, device="
 
 def same_params(a, b):
     return (a.k or 1) == (b.k or 1) and a.N == b.N and a.l == b.l and a.split.top_l1 == b.split.top_l1 \
-        and a.split.leaf_log2 == b.split.leaf_log2
+        and a.split.leaf_log2 == b.split.leaf_log2 and a.pad_rows == b.pad_rows
 
 
 def policy_times(reqs, timings, model=None):
