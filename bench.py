@@ -405,6 +405,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-products measurement")
+    ap.add_argument("--no-padded", action="store_true",
+                    help="skip the whole-row padded run of the large product (profiles of the unpadded one)")
     ap.add_argument("--split-sweep", action="store_true",
                     help="instead of the benchmark: cache-friendly vs divide-and-conquer transforms over a sweep "
                          "of Z[x] products with 8000-bit coefficients (one JSON line)")
@@ -497,7 +499,8 @@ def main():
             "avg_launch_ms": round(leaf_ms / max(1, launches), 4),
         },
     }
-    line["whole_row_padding"] = _leg(lambda: padded_leg(T, torch, dg, dh, out, l, n, reps=3))
+    if not args.no_padded:
+        line["whole_row_padding"] = _leg(lambda: padded_leg(T, torch, dg, dh, out, l, n, reps=3))
     del out, ws, dg, dh
     torch.cuda.empty_cache()
     # a failing secondary leg is reported in the line (with its traceback on
