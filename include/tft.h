@@ -140,7 +140,7 @@ int pointwise_mul(const tft_ring *ring, uint64_t n, const void *a, const void *b
  *          with L2 = L/L1 (the zero-padding of Sect. 6): TFT(g), TFT(h) give n'
  *          values, n' pointwise products, ITFT(L, 1, n', n', 0).  The ITFT then
  *          has no partial last row.  Cells n..n'-1 of the product are zero, so
- *          the result is identical. */
+ *          the result is identical.  Other values: TFT_E_ARG. */
 typedef struct {
     uint32_t N;
     uint32_t l;

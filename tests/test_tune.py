@@ -82,3 +82,10 @@ def test_pass_count_features_match_the_planner(lg, lh, N, l, top, leaf, pad):
     pt = max(len(T.Plan(ring, 0, l, 0, z, nt, 0, top, leaf).export()["passes"]) for z in (lg, lh))
     pi = len(T.Plan(ring, 1, l, 0, nt, nt, 0, top, leaf).export()["passes"])
     assert round(f[10] * 8) == pt and round(f[12] * 32) == pi, (f[10] * 8, pt, f[12] * 32, pi)
+
+
+def test_padding_flag_validated():
+    base = T.zx_mul_ss_workspace(300, 4, 200, 4, T.SSParams(0, 0, T.Split(0, 0), 1, 0))
+    assert T.zx_mul_ss_workspace(300, 4, 200, 4, T.SSParams(0, 0, T.Split(0, 0), 1, 1)) == base
+    with pytest.raises(T.TFTError):
+        T.zx_mul_ss_workspace(300, 4, 200, 4, T.SSParams(0, 0, T.Split(0, 0), 1, 2))
