@@ -212,21 +212,21 @@ def test_whole_row_padding_pass_counts_large_case():
 # base-case counts (Theorems 1 and 2)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("leaf_log2", [1, 0])
-def test_base_case_counts_within_theorem_bounds(leaf_log2):
-    rng = random.Random(leaf_log2 + 9)
+@pytest.mark.parametrize("leaf_log2,top", [(1, 0), (0, 0), (1, T.SPLIT_DC), (3, T.SPLIT_DC)])
+def test_base_case_counts_within_theorem_bounds(leaf_log2, top):
+    rng = random.Random(leaf_log2 + 9 + (top & 1))
     ring = T.fermat_ring(2048)  # ord 4096
     for l in range(1, 13):
         L = 1 << l
         for _ in range(6):
             z, n = rng.randint(1, L), rng.randint(1, L)
-            p = T.Plan(ring, 0, l, 0, z, n, 0, 0, leaf_log2)
+            p = T.Plan(ring, 0, l, 0, z, n, 0, top, leaf_log2)
             # Theorem 1: at most min((n-1) l/2 + L - 1, L l/2)
             assert 2 * p.base_cases <= min((n - 1) * l + 2 * (L - 1), L * l), (l, z, n, p.base_cases)
             zi = rng.randint(1, L)
             ni = rng.randint(0, zi)
             f = 1 if ni == 0 else (0 if ni == L else rng.randint(0, 1))
-            q = T.Plan(ring, 1, l, 0, zi, ni, f, 0, leaf_log2)
+            q = T.Plan(ring, 1, l, 0, zi, ni, f, top, leaf_log2)
             # Theorem 2: at most min((n+f-1) l/2 + L - 1, L l/2)
             assert 2 * q.base_cases <= min((ni + f - 1) * l + 2 * (L - 1), L * l), (l, zi, ni, f, q.base_cases)
 
