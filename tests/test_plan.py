@@ -103,6 +103,58 @@ def test_every_top_split_gives_the_same_outputs(top_l1):
         _check_itft(FERMAT, l, rng.randrange(128), zi, ni, f, top_l1, 2, seed=zi + 100 * ni)
 
 
+def _column_outputs(ring, l, l1, s, z, a, rows):
+    """Eq. (b-cols): output i1 < rows of the column transform of column u, i.e.
+    TFT(L1, zeta omega_L^u, z_u, rows) of a_u, a_{u+L2}, ... (a_i = 0 for i >= z)."""
+    L, L1, L2 = 1 << l, 1 << l1, 1 << (l - l1)
+    z1, z2 = divmod(z, L2)
+    b = {}
+    for u in range(L2 if z1 else z2):
+        col = [a[u + j * L2] for j in range(L1) if u + j * L2 < z]
+        for i1, v in enumerate(O.tft(ring, L1, s + (ring.ord // L) * u, len(col), rows, col)):
+            b[(i1, u)] = v
+    return b
+
+
+def _first_pass(plan, ring, x, seed):
+    d = plan.export()
+    return simulate(dict(d, passes=d["passes"][:1]), ring, x, seed), len(d["passes"])
+
+
+@pytest.mark.parametrize("z,n,s", [(64, 64, 0), (41, 57, 5), (9, 30, 100), (64, 17, 77)])
+def test_tft_column_pass_state_is_eq_b_cols(z, n, s):
+    """After the top-level column pass of Alg. 1 (L1 = L2 = 8, leaves of 8 cells),
+    cell (i1, u) holds eq. (b-cols) for i1 < n1' and u < z2'."""
+    ring, l, l1 = FERMAT, 6, 3
+    L2 = 1 << (l - l1)
+    rng = random.Random(z * 7 + n)
+    a = [_rand(ring, rng) for _ in range(1 << l)]
+    rows = -(-n // L2)
+    x, npass = _first_pass(T.Plan(_lib_ring(ring), 0, l, s, z, n, 0, l1, 3), ring, list(a), 3)
+    assert npass == 2
+    b = _column_outputs(ring, l, l1, s, z, a, rows)
+    for (i1, u), v in b.items():
+        assert x[i1 * L2 + u] == v, (i1, u)
+
+
+@pytest.mark.parametrize("n,s", [(64, 0), (57, 9), (16, 3), (40, 120)])
+def test_itft_row_phase_state_is_l2_b(n, s):
+    """After the full-row phase of Alg. 2 (z = n, f = 0), full row u < n1 holds
+    L2 times the column-pass values b of eq. (b-cols) (the invariant of Sect. 4)."""
+    ring, l, l1 = FERMAT, 6, 3
+    L2, l2 = 1 << (l - l1), l - l1
+    rng = random.Random(n + 1000 * s)
+    a = [_rand(ring, rng) for _ in range(n)]
+    inputs, _ = O.itft_case(ring, 1 << l, s, n, n, 0, a)
+    x = list(inputs) + [_rand(ring, rng) for _ in range((1 << l) - n)]
+    x, _ = _first_pass(T.Plan(_lib_ring(ring), 1, l, s, n, n, 0, l1, 3), ring, x, 4)
+    n1 = n // L2
+    b = _column_outputs(ring, l, l1, s, n, a + [0] * ((1 << l) - n), n1)
+    for u in range(n1):
+        for i2 in range(L2):
+            assert x[u * L2 + i2] == ring.mul_theta(b[(u, i2)], l2), (u, i2)
+
+
 @pytest.mark.parametrize("leaf_log2", [1, 2, 3])
 def test_divide_and_conquer_split_gives_the_same_outputs(leaf_log2):
     """L1 = 2 at every level above the leaf (van der Hoeven's order, Sect. 1)."""
