@@ -122,6 +122,28 @@ def test_itft_multipass(N, leaf):
             _run_itft(N, l, rng.randrange(2 * N), z, n, f, seed=z + n, leaf_log2=leaf)
 
 
+@pytest.mark.parametrize("N", [32, 64, 512, 2048, 65536])
+def test_shift_edges(N):
+    """Length-2 transforms multiply one cell by theta^s directly: every shift class
+    (0, 1, 31, 32, N-1, N, 2N-1) on all-ones, 2^N, 0 and 1 operands."""
+    ring = O.FermatRing(N)
+    ones, top = (1 << N) - 1, ring.p - 1
+    rng = random.Random(N + 5)
+    pairs = [(ones, ones), (top, 1), (0, top), (top, top), (rng.randrange(ring.p), ones), (1, ones)]
+    for s in sorted({0, 1, 31, 32, N - 1, N, 2 * N - 1}):
+        note("shift edges N=%d s=%d" % (N, s))
+        for a0, a1 in pairs:
+            x = fermat_to_device([a0, a1], N, 2, torch)
+            T.tft_forward(T.fermat_ring(N), 1, s, 2, 2, x)
+            torch.cuda.synchronize()
+            assert fermat_values(*fermat_from_device(x, N, 2, 2)) == O.tft(ring, 2, s, 2, 2, [a0, a1]), (s, a0, a1)
+            inputs, expect = O.itft_case(ring, 2, s, 2, 2, 0, [a0, a1])
+            y = fermat_to_device(list(inputs), N, 2, torch)
+            T.itft_inverse(T.fermat_ring(N), 1, s, 2, 2, 0, y)
+            torch.cuda.synchronize()
+            assert fermat_values(*fermat_from_device(y, N, 2, 2)) == expect, (s, a0, a1)
+
+
 LARGE_RINGS = [16384, 32768, 131072]  # 512, 1024 and 4096 limbs a cell
 
 
