@@ -29,6 +29,8 @@ if ROOT not in sys.path:
 
 METRIC = "TFT+ITFT GB/s & % HBM peak; batched Z[x] muls/s vs one-at-a-time (bit-exact)"
 HBM_PEAK_GBS = 8000.0
+# 256 CUs x 16 lanes per clock (v_mad_u64_u32 issues at a quarter of the 64-lane rate) x 2.4 GHz
+MAD_PEAK_T = 256 * 16 * 2.4e9 / 1e12
 
 
 def _split(l):
@@ -497,6 +499,17 @@ def main():
             "alg_bytes_per_launch": int(alg_bytes / max(1, launches)),
             "kernel": "fermat_leaf_kernel<64,32> (%d launches per step)" % launches,
             "avg_launch_ms": round(leaf_ms / max(1, launches), 4),
+        },
+        # the pointwise stage is bound by the 32 x 32 -> 64-bit multiply-add
+        # (v_mad_u64_u32, quarter rate: 16 lanes per CU per clock)
+        "pointwise_roofline": {
+            "bound": "alu",
+            "achieved": round(n * (N // 32) ** 2 / (avg("pointwise_ms") * 1e-3) / 1e12, 3),
+            "peak": round(MAD_PEAK_T, 3),
+            "unit": "T limb multiply-adds/s",
+            "frac": round(n * (N // 32) ** 2 / (avg("pointwise_ms") * 1e-3) / 1e12 / MAD_PEAK_T, 4),
+            "kernel": "fermat_pointwise_kernel<64,32>: %d products of %d x %d limbs (schoolbook)" % (n, N // 32,
+                                                                                                  N // 32),
         },
     }
     if not args.no_padded:
