@@ -1,0 +1,48 @@
+"""Host-side parts of bench.py (no GPU): the algorithmic cell counts behind the
+GB/s metric, the multiply-add peak, and the refusal of more than one GPU."""
+
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+# (l, z, n) -> cells of one TFT (z = operand length) and of the ITFT (z = n, f = 0),
+# counted from the top-level loops of Alg. 1 and Alg. 2 with the paper's split
+@pytest.mark.parametrize("l,z,n,tft,itft", [
+    (10, 500, 999, 3547, 4046),
+    (13, 3000, 5999, 21031, 24030),
+    (17, 50000, 99999, 350703, 400702),
+    (11, 977, 1953, 6898, 7874),
+])
+def test_algorithmic_cells(l, z, n, tft, itft):
+    assert bench.alg_cells_tft(l, z, n) == tft
+    assert bench.alg_cells_itft(l, n, n, 0) == itft
+
+
+def test_large_product_bytes():
+    cells = 2 * bench.alg_cells_tft(17, 50000, 99999) + bench.alg_cells_itft(17, 99999, 99999, 0)
+    assert cells == 1102108 and cells * 8192 == 9028468736
+
+
+def test_full_transform_reads_and_writes_every_cell_twice():
+    # z = n = L: every column and every row pass reads and writes all L cells
+    for l in (4, 7, 10):
+        L = 1 << l
+        assert bench.alg_cells_tft(l, L, L) == 4 * L
+        assert bench.alg_cells_itft(l, L, L, 0) == 4 * L
+
+
+def test_mad_peak():
+    assert abs(bench.MAD_PEAK_T - 9.8304) < 1e-9
+
+
+def test_more_than_one_gpu_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
