@@ -313,24 +313,27 @@ def other_products(T, torch, reps=5):
     return out
 
 
-def padded_leg(T, torch, dg, dh, out, l, n, reps=3):
+def padded_leg(T, torch, dg, dh, out, l, n, N, reps=3):
     """The same product with n rounded up to whole rows of the paper split
-    (Sect. 6 zero-padding: no partial last row in the ITFT); the output must
-    equal the unpadded one bit for bit."""
-    p = T.SSParams(0, 0, T.Split(0, 0), 1, 1)
+    (Sect. 6 zero-padding: no partial last row in the ITFT), with the forward
+    twist zeta = theta^(3N/2) (the ITFT then takes zeta^2), and with both; every
+    output must equal the plain one bit for bit."""
     L2 = 1 << (l - l // 2)
-    ws = torch.empty(T.zx_mul_ss_workspace(dg.shape[0], dg.shape[1], dh.shape[0], dh.shape[1], p),
-                     dtype=torch.uint8, device="cuda")
-    o = torch.empty_like(out)
-    T.zx_mul_ss_timed(dg, dh, o, p, ws=ws)
-    runs = sorted((T.zx_mul_ss_timed(dg, dh, o, p, ws=ws) for _ in range(reps)), key=lambda t: t["total_ms"])
-    t = runs[len(runs) // 2]
-    same = bool(torch.equal(o, out))
-    del ws, o
-    return {"n_padded": -(-n // L2) * L2, "total_ms": round(t["total_ms"], 3),
-            "transform_ms": round(t["tft_g_ms"] + t["tft_h_ms"] + t["itft_ms"], 3), "itft_ms": round(t["itft_ms"], 3),
-            "pointwise_ms": round(t["pointwise_ms"], 3), "leaf_launches": t["leaf_launches"],
-            "same_output_as_unpadded": same}
+    res = {"n_padded": -(-n // L2) * L2, "zeta_exp": 3 * N // 2}
+    for name, pad, zexp in (("padded", 1, 0), ("twisted", 0, 3 * N // 2), ("padded_twisted", 1, 3 * N // 2)):
+        p = T.SSParams(0, 0, T.Split(0, 0), 1, pad, zexp)
+        ws = torch.empty(T.zx_mul_ss_workspace(dg.shape[0], dg.shape[1], dh.shape[0], dh.shape[1], p),
+                         dtype=torch.uint8, device="cuda")
+        o = torch.empty_like(out)
+        T.zx_mul_ss_timed(dg, dh, o, p, ws=ws)
+        runs = sorted((T.zx_mul_ss_timed(dg, dh, o, p, ws=ws) for _ in range(reps)), key=lambda t: t["total_ms"])
+        t = runs[len(runs) // 2]
+        res[name] = {"total_ms": round(t["total_ms"], 3),
+                     "transform_ms": round(t["tft_g_ms"] + t["tft_h_ms"] + t["itft_ms"], 3),
+                     "tft_ms": round(t["tft_g_ms"] + t["tft_h_ms"], 3), "itft_ms": round(t["itft_ms"], 3),
+                     "leaf_launches": t["leaf_launches"], "same_output": bool(torch.equal(o, out))}
+        del ws, o
+    return res
 
 
 def split_sweep(T, torch, bits=8000, lo=512, hi=16384, step=1.05, reps=3):
@@ -408,7 +411,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-products measurement")
     ap.add_argument("--no-padded", action="store_true",
-                    help="skip the whole-row padded run of the large product (profiles of the unpadded one)")
+                    help="skip the padded and twisted runs of the large product (profiles of the plain one)")
     ap.add_argument("--split-sweep", action="store_true",
                     help="instead of the benchmark: cache-friendly vs divide-and-conquer transforms over a sweep "
                          "of Z[x] products with 8000-bit coefficients (one JSON line)")
@@ -513,7 +516,7 @@ def main():
         },
     }
     if not args.no_padded:
-        line["whole_row_padding"] = _leg(lambda: padded_leg(T, torch, dg, dh, out, l, n, reps=3))
+        line["product_variants"] = _leg(lambda: padded_leg(T, torch, dg, dh, out, l, n, N, reps=3))
     del out, ws, dg, dh
     torch.cuda.empty_cache()
     # a failing secondary leg is reported in the line (with its traceback on

@@ -140,13 +140,21 @@ int pointwise_mul(const tft_ring *ring, uint64_t n, const void *a, const void *b
  *          with L2 = L/L1 (the zero-padding of Sect. 6): TFT(g), TFT(h) give n'
  *          values, n' pointwise products, ITFT(L, 1, n', n', 0).  The ITFT then
  *          has no partial last row.  Cells n..n'-1 of the product are zero, so
- *          the result is identical.  Other values: TFT_E_ARG. */
+ *          the result is identical.  Other values: TFT_E_ARG.
+ *   zeta_exp  TFT(g) and TFT(h) use zeta = theta^s, s = zeta_exp mod 2N, instead of
+ *          Sect. 2's zeta = 1, and the ITFT uses zeta^2: by eq. (1) each forward
+ *          output j carries zeta^[j], so product j carries zeta^(2[j]), which is
+ *          the weighting of TFT(L, zeta^2) of u; the ITFT with zeta^2 then returns
+ *          L u exactly, and every value gives the same product.  About 3N/2 moves
+ *          operands that fill less than half an element into its empty half at the
+ *          first butterflies, which shortens carry runs there. */
 typedef struct {
     uint32_t N;
     uint32_t l;
     tft_split split;
     uint32_t k;
     uint32_t pad_rows;
+    uint32_t zeta_exp;
 } tft_ss_params;
 
 /* Workspace bytes zx_mul_ss needs for these operand shapes and parameters. */

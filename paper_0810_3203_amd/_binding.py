@@ -53,7 +53,7 @@ class SSTiming(ctypes.Structure):
 
 class SSParams(ctypes.Structure):
     _fields_ = [("N", ctypes.c_uint32), ("l", ctypes.c_uint32), ("split", Split), ("k", ctypes.c_uint32),
-                ("pad_rows", ctypes.c_uint32)]
+                ("pad_rows", ctypes.c_uint32), ("zeta_exp", ctypes.c_uint32)]
 
 
 class ZXRequest(ctypes.Structure):

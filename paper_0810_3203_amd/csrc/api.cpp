@@ -445,9 +445,9 @@ static int ss_run(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uin
     tft_split sp = params ? params->split : tft_split{0, 0};
     if (!sp.leaf_log2) sp.leaf_log2 = ss_leaf_log2(sh.N, sh.l);
     const tft_split *split = &sp;
-    tft_plan *pg = cached_plan(&ring, 0, sh.l, 0, sh.zg, sh.nt, 0, split);
-    tft_plan *ph = cached_plan(&ring, 0, sh.l, 0, sh.zh, sh.nt, 0, split);
-    tft_plan *pi = cached_plan(&ring, 1, sh.l, 0, sh.nt, sh.nt, 0, split);
+    tft_plan *pg = cached_plan(&ring, 0, sh.l, sh.s, sh.zg, sh.nt, 0, split);
+    tft_plan *ph = cached_plan(&ring, 0, sh.l, sh.s, sh.zh, sh.nt, 0, split);
+    tft_plan *pi = cached_plan(&ring, 1, sh.l, (2ull * sh.s) % (2ull * sh.N), sh.nt, sh.nt, 0, split);
     hipEvent_t ev[7] = {};
     LaunchTimer lt;
     LaunchTimer *ltp = tm ? &lt : nullptr;

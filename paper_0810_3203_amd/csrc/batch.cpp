@@ -215,14 +215,15 @@ int tft_batch_plan_create(const tft_zx_request *reqs, uint32_t count, uint64_t m
             Group G;
             G.W = kv.first;
             const uint32_t ord = 64u * G.W;
-            std::map<std::tuple<uint32_t, uint32_t, uint64_t, uint64_t, uint32_t, uint32_t>, std::pair<Schedule, uint32_t>>
+            std::map<std::tuple<uint32_t, uint32_t, uint32_t, uint64_t, uint64_t, uint32_t, uint32_t>,
+                     std::pair<Schedule, uint32_t>>
                 cache;
-            auto sched = [&](uint32_t dir, uint32_t l, uint64_t z, uint64_t n, uint32_t top,
+            auto sched = [&](uint32_t dir, uint32_t l, uint32_t s, uint64_t z, uint64_t n, uint32_t top,
                              uint32_t leaf) -> const std::pair<Schedule, uint32_t> & {
-                auto key = std::make_tuple(dir, l, z, n, top, leaf);
+                auto key = std::make_tuple(dir, l, s, z, n, top, leaf);
                 auto it = cache.find(key);
                 if (it != cache.end()) return it->second;
-                Schedule S = build_schedule(dir, l, ord, 0, z, n, 0, leaf, top);
+                Schedule S = build_schedule(dir, l, ord, s, z, n, 0, leaf, top);
                 const uint32_t off = append_programs(G, S);
                 return cache.emplace(key, std::make_pair(std::move(S), off)).first->second;
             };
@@ -239,9 +240,9 @@ int tft_batch_plan_create(const tft_zx_request *reqs, uint32_t count, uint64_t m
                 if (r.params.split.leaf_log2)
                     leaf = std::min(fermat_max_leaf_log2(G.W), std::max<uint32_t>(1, r.params.split.leaf_log2));
                 const uint32_t top = r.params.split.top_l1;
-                sg.push_back(&sched(0, s.l, s.zg, s.nt, top, leaf));
-                sh.push_back(&sched(0, s.l, s.zh, s.nt, top, leaf));
-                si.push_back(&sched(1, s.l, s.nt, s.nt, top, leaf));
+                sg.push_back(&sched(0, s.l, s.s, s.zg, s.nt, top, leaf));
+                sh.push_back(&sched(0, s.l, s.s, s.zh, s.nt, top, leaf));
+                si.push_back(&sched(1, s.l, (uint32_t)((2ull * s.s) % ord), s.nt, s.nt, top, leaf));
             }
             const uint32_t G64 = 64u / std::min<uint32_t>(G.W, 64u);
             auto merge = [&](std::vector<Pass> &out, const std::vector<std::vector<const std::pair<Schedule, uint32_t> *>> &lists,

@@ -14,6 +14,7 @@ struct SSShape {
     uint32_t N, W, l, k, ws;
     uint64_t zg, zh, n, L, bytes;
     uint64_t nt;    // truncation of the transforms: n, or n rounded up to whole top-level rows
+    uint32_t s;     // twist of TFT(g), TFT(h): zeta = theta^s, s < 2N; the ITFT takes zeta^2
     uint64_t bits;  // bound on the bits of an output coefficient
 };
 
@@ -62,6 +63,7 @@ inline int ss_shape(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h
     o->zh = zh;
     o->n = n;
     o->nt = n;
+    o->s = p ? (uint32_t)(p->zeta_exp % (2ull * W * 32)) : 0u;
     if (p && p->pad_rows) {
         if (p->pad_rows > 1) return TFT_E_ARG;
         // rows of the top split (Alg. 1, Alg. 2): L2 = 2^(l - l1)

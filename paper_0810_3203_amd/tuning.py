@@ -59,7 +59,7 @@ def train_model(X, y, hidden=64, depth=3, iters=3000, lr=2e-3, seed=11, device="
 
 def same_params(a, b):
     return (a.k or 1) == (b.k or 1) and a.N == b.N and a.l == b.l and a.split.top_l1 == b.split.top_l1 \
-        and a.split.leaf_log2 == b.split.leaf_log2 and a.pad_rows == b.pad_rows
+        and a.split.leaf_log2 == b.split.leaf_log2 and a.pad_rows == b.pad_rows and a.zeta_exp == b.zeta_exp
 
 
 def policy_times(reqs, timings, model=None):

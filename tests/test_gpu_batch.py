@@ -119,7 +119,8 @@ def _mixed_requests(seed=2024):
     choices = [None, T.SSParams(0, 0, T.Split(0, 0), 1), T.SSParams(0, 0, T.Split(0, 0), 2),
                T.SSParams(0, 0, T.Split(0, 0), 4), T.SSParams(0, 0, T.Split(0, 0), 8),
                T.SSParams(0, 0, T.Split(2, 0), 2), T.SSParams(0, 0, T.Split(0, 3), 1),
-               T.SSParams(0, 0, T.Split(0, 0), 1, 1), T.SSParams(0, 0, T.Split(T.SPLIT_DC, 0), 2, 1)]
+               T.SSParams(0, 0, T.Split(0, 0), 1, 1), T.SSParams(0, 0, T.Split(T.SPLIT_DC, 0), 2, 1),
+               T.SSParams(0, 0, T.Split(0, 0), 2, 1, 3 << 20)]
     for i in range(21):
         bits = rng.choice([32, 64, 96, 1000])
         hi = 150 if bits == 1000 else 600

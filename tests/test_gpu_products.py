@@ -101,6 +101,19 @@ def test_zx_whole_row_padding(coracle):
         _check_sampled(coracle, g, h, got, ow, range(1000))
 
 
+def test_zx_twisted_transforms(coracle):
+    """TFT(g), TFT(h) twisted by zeta = theta^s and the ITFT by zeta^2 give the same product."""
+    from synth.splitmix import SplitMix64
+    s = SplitMix64(80)
+    g, h = wl.random_ints(s, 500, 200), wl.random_ints(s, 433, 200)
+    for N, zexp, pad in [(0, 1, 0), (16384, 24576, 0), (16384, 24576, 1), (16384, 32767, 0), (0, 12345, 1),
+                         (16384, 1 << 31, 0)]:
+        p = T.SSParams(N, 0, T.Split(0, 0), 1, pad, zexp)
+        note("zx_mul_ss twist s=%d N=%d pad=%d" % (zexp, N, pad))
+        got, ow = _zx_gpu(g, h, p)
+        _check_sampled(coracle, g, h, got, ow, range(932))
+
+
 def test_zx_case1_full(coracle):
     g, h = wl.zx_operands(1)
     note("zx_mul_ss case 1 (500 x 500, 64-bit)")

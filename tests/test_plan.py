@@ -224,6 +224,24 @@ def test_polynomial_product_through_the_schedule():
     assert [ring.mul(v, ring.inv_pow2(l)) for v in u[:n]] == O.zx_mul(g, h)
 
 
+@pytest.mark.parametrize("s", [1, 77, 96, 127])
+def test_any_twist_gives_the_same_product(s):
+    """Sect. 2 with TFT(g), TFT(h) twisted by zeta = theta^s: by eq. (1) product j
+    carries zeta^(2 j'), so the ITFT with zeta^2 still returns L (g h)."""
+    ring = FERMAT
+    rng = random.Random(s)
+    l, L = 6, 64
+    g = [rng.randrange(1 << 20) for _ in range(25)]
+    h = [rng.randrange(1 << 20) for _ in range(19)]
+    n = len(g) + len(h) - 1
+    xg = simulate(T.Plan(_lib_ring(ring), 0, l, s, len(g), n, 0, 0, 2).export(), ring, g + [0] * (L - len(g)))
+    xh = simulate(T.Plan(_lib_ring(ring), 0, l, s, len(h), n, 0, 0, 2).export(), ring, h + [0] * (L - len(h)))
+    assert xg[:n] == O.tft(ring, L, s, len(g), n, g)
+    u = [ring.mul(a, b) for a, b in zip(xg[:n], xh[:n])] + [0] * (L - n)
+    u = simulate(T.Plan(_lib_ring(ring), 1, l, 2 * s, n, n, 0, 0, 2).export(), ring, u)
+    assert [ring.mul(v, ring.inv_pow2(l)) for v in u[:n]] == O.zx_mul(g, h)
+
+
 @pytest.mark.parametrize("top_l1", [0, 2, T.SPLIT_DC])
 def test_whole_row_padding_through_the_schedule(top_l1):
     """Sect. 6 zero-padding: with n rounded up to whole rows of the top split the
