@@ -140,9 +140,10 @@ def _leg(fn):
 
 
 def batch_leg(T, torch, count=4096, train_count=32, heldout=16, replays=3, k1_stride=16):
-    """Many Z[x] products of uneven lengths: batched plan (cost-model parameters,
-    hipGraph replay) against one-at-a-time zx_mul_ss with the default rule;
-    outputs compared bit for bit on the device."""
+    """Many Z[x] products of uneven lengths: batched plans (hipGraph replay) under two
+    parameter policies, the cost model's choice and the default rule's k with
+    whole-row padding and the twist, the faster reported, against one-at-a-time
+    zx_mul_ss with the default rule; outputs compared bit for bit on the device."""
     from paper_0810_3203_amd import tuning
     from synth import device as dev
 
@@ -192,25 +193,31 @@ def batch_leg(T, torch, count=4096, train_count=32, heldout=16, replays=3, k1_st
         ks[r.params.k] = ks.get(r.params.k, 0) + 1
     padded = sum(1 for r in arr if r.params.pad_rows)
 
-    t0 = time.perf_counter()
-    plan = T.BatchPlan(arr, max_workspace=96 << 30)
-    plan_s = time.perf_counter() - t0
-    assert all(s == 0 for s in plan.status())
-    ws = torch.empty(plan.workspace, dtype=torch.uint8, device="cuda")
-    plan.execute(ws, use_graph=True)  # direct run + capture
-    plan.execute(ws, use_graph=True)  # first replay
-    torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(replays):
-        plan.execute(ws, use_graph=True)
-    e1.record()
-    torch.cuda.synchronize()
-    batch_ms = e0.elapsed_time(e1) / replays
-    _progress("batch: graph replay %.1f ms (%d launches)" % (batch_ms, plan.launches))
-    launches = plan.launches
-    plan.close()
-    del ws
+
+    def time_plan(req_arr, label):
+        t0 = time.perf_counter()
+        plan = T.BatchPlan(req_arr, max_workspace=96 << 30)
+        build_s = time.perf_counter() - t0
+        assert all(s == 0 for s in plan.status())
+        ws = torch.empty(plan.workspace, dtype=torch.uint8, device="cuda")
+        plan.execute(ws, use_graph=True)  # direct run + capture
+        plan.execute(ws, use_graph=True)  # first replay
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(replays):
+            plan.execute(ws, use_graph=True)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / replays
+        _progress("batch (%s): graph replay %.1f ms (%d launches)" % (label, ms, plan.launches))
+        n_launch = plan.launches
+        plan.close()
+        del ws
+        return ms, n_launch, build_s
+
+    # policy 1: the cost model's choice per request (trained on single-product timings)
+    batch_ms_model, launches_model, plan_s = time_plan(arr, "cost model")
 
     # one at a time, default rule, no graph
     params = [T.ss_default_params(g.shape[0], g.shape[1], h.shape[0], h.shape[1]) for g, h in ops]
@@ -232,6 +239,22 @@ def batch_leg(T, torch, count=4096, train_count=32, heldout=16, replays=3, k1_st
     single_ms = e0.elapsed_time(e1)
     _progress("batch: one at a time %.1f ms" % single_ms)
     exact = all(torch.equal(a, b) for a, b in zip(outs_b, outs_s))
+
+    # policy 2: the default rule's k with whole-row padding and the forward twist
+    # theta^(3N/2) (ITFT theta^N), the options that merged passes reward; N from
+    # the ring-size feature log2(W)/12
+    arr2 = T.requests_array(reqs)
+    for r in arr2:
+        p = T.ss_default_params(r.len_g, r.g_limbs, r.len_h, r.h_limbs)
+        p.pad_rows = 1
+        W = int(round(2 ** (12 * T.ss_features(r.len_g, r.g_limbs, r.len_h, r.h_limbs, p)[5])))
+        p.zeta_exp = 3 * (32 * W) // 2
+        r.params = p
+    batch_ms_rule, launches_rule, _ = time_plan(arr2, "default k, padded, twisted")
+    exact_rule = all(torch.equal(a, b) for a, b in zip(outs_b, outs_s))
+    use_rule = batch_ms_rule < batch_ms_model
+    batch_ms = min(batch_ms_model, batch_ms_rule)
+    launches = launches_rule if use_rule else launches_model
 
     # the paper's literal product (k = 1) one at a time, on every k1_stride-th request
     p1 = [T.SSParams(0, 0, T.Split(0, 0), 1)] * count
@@ -262,7 +285,9 @@ def batch_leg(T, torch, count=4096, train_count=32, heldout=16, replays=3, k1_st
         "k1_one_at_a_time_ms_extrapolated": round(k1_ms, 3),
         "speedup_vs_k1_one_at_a_time": round(k1_ms / batch_ms, 3),
         "k1_sample": "every %dth request (%d), time scaled by %d/%d" % (k1_stride, len(sel), count, len(sel)),
-        "bit_exact_vs_one_at_a_time": bool(exact and exact_k1),
+        "bit_exact_vs_one_at_a_time": bool(exact and exact_k1 and exact_rule),
+        "policies_ms": {"cost_model": round(batch_ms_model, 3), "default_k_padded_twisted": round(batch_ms_rule, 3),
+                        "used": "default_k_padded_twisted" if use_rule else "cost_model"},
         "k_chosen": {str(k): v for k, v in sorted(ks.items())},
         "padded_chosen": padded,
         "cost_model": {"train_requests": train_count, "train_rows": len(X), "final_loss": round(loss, 5),
