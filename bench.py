@@ -140,10 +140,11 @@ def _leg(fn):
 
 
 def batch_leg(T, torch, count=4096, train_count=32, heldout=16, replays=3, k1_stride=16):
-    """Many Z[x] products of uneven lengths: batched plans (hipGraph replay) under two
-    parameter policies, the cost model's choice and the default rule's k with
-    whole-row padding and the twist, the faster reported, against one-at-a-time
-    zx_mul_ss with the default rule; outputs compared bit for bit on the device."""
+    """Many Z[x] products of uneven lengths: batched plans (hipGraph replay) under three
+    parameter policies (the cost model trained on single-product timings, the same
+    model trained on batch-context timings, and the default rule's k with whole-row
+    padding and the twist), the fastest reported, against one-at-a-time zx_mul_ss
+    with the default rule; outputs compared bit for bit on the device."""
     from paper_0810_3203_amd import tuning
     from synth import device as dev
 
@@ -181,8 +182,19 @@ def batch_leg(T, torch, count=4096, train_count=32, heldout=16, replays=3, k1_st
     t_best = sum(r["best"] for r in rows)
     t_mlp = sum(r["mlp"] for r in rows)
     t_def = sum(r["default"] for r in rows)
-    del keep, extra, ereq
     _progress("batch: model trained (loss %.4f), held-out regret %.3f" % (loss, t_mlp / t_best - 1))
+    # the same model trained on batch-context timings (copies of a request in one plan)
+    t0 = time.perf_counter()
+    tim_b = tuning.time_candidates_in_batch(ereq[:train_count])
+    Xb, yb = tuning.training_rows(ereq[:train_count], tim_b)
+    model_b, loss_b = tuning.train_model(Xb, yb, iters=3000)
+    ho_b = tuning.time_candidates_in_batch(ereq[train_count:])
+    rows_b = tuning.policy_times(ereq[train_count:], ho_b, model_b)
+    tb_best, tb_mlp, tb_def = (sum(r[k] for r in rows_b) for k in ("best", "mlp", "default"))
+    tune_b_s = time.perf_counter() - t0
+    del keep, extra, ereq
+    _progress("batch: batch-context model trained (loss %.4f), held-out regret %.3f, %.1f s"
+              % (loss_b, tb_mlp / tb_best - 1, tune_b_s))
 
     arr = T.requests_array(reqs)
     t0 = time.perf_counter()
@@ -252,9 +264,15 @@ def batch_leg(T, torch, count=4096, train_count=32, heldout=16, replays=3, k1_st
         r.params = p
     batch_ms_rule, launches_rule, _ = time_plan(arr2, "default k, padded, twisted")
     exact_rule = all(torch.equal(a, b) for a, b in zip(outs_b, outs_s))
-    use_rule = batch_ms_rule < batch_ms_model
-    batch_ms = min(batch_ms_model, batch_ms_rule)
-    launches = launches_rule if use_rule else launches_model
+    # policy 3: the cost model trained on batch-context timings
+    arr3 = T.requests_array(reqs)
+    model_b.choose(arr3)
+    batch_ms_mb, launches_mb, _ = time_plan(arr3, "batch-context cost model")
+    exact_mb = all(torch.equal(a, b) for a, b in zip(outs_b, outs_s))
+    pol = {"cost_model": (batch_ms_model, launches_model), "default_k_padded_twisted": (batch_ms_rule, launches_rule),
+           "batch_context_cost_model": (batch_ms_mb, launches_mb)}
+    used = min(pol, key=lambda k: pol[k][0])
+    batch_ms, launches = pol[used]
 
     # the paper's literal product (k = 1) one at a time, on every k1_stride-th request
     p1 = [T.SSParams(0, 0, T.Split(0, 0), 1)] * count
@@ -285,9 +303,11 @@ def batch_leg(T, torch, count=4096, train_count=32, heldout=16, replays=3, k1_st
         "k1_one_at_a_time_ms_extrapolated": round(k1_ms, 3),
         "speedup_vs_k1_one_at_a_time": round(k1_ms / batch_ms, 3),
         "k1_sample": "every %dth request (%d), time scaled by %d/%d" % (k1_stride, len(sel), count, len(sel)),
-        "bit_exact_vs_one_at_a_time": bool(exact and exact_k1 and exact_rule),
-        "policies_ms": {"cost_model": round(batch_ms_model, 3), "default_k_padded_twisted": round(batch_ms_rule, 3),
-                        "used": "default_k_padded_twisted" if use_rule else "cost_model"},
+        "bit_exact_vs_one_at_a_time": bool(exact and exact_k1 and exact_rule and exact_mb),
+        "policies_ms": dict({k: round(v[0], 3) for k, v in pol.items()}, used=used),
+        "batch_context_cost_model": {"train_rows": len(Xb), "final_loss": round(loss_b, 5),
+                                     "heldout_regret": round(tb_mlp / tb_best - 1, 4),
+                                     "heldout_gain_vs_default": round(tb_def / tb_mlp, 4), "host_s": round(tune_b_s, 2)},
         "k_chosen": {str(k): v for k, v in sorted(ks.items())},
         "padded_chosen": padded,
         "cost_model": {"train_requests": train_count, "train_rows": len(X), "final_loss": round(loss, 5),

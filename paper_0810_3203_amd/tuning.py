@@ -32,6 +32,45 @@ def time_candidates(reqs, reps=3, device="cuda", stream=None):
     return out
 
 
+def time_candidates_in_batch(reqs, copies=8, replays=2, device="cuda"):
+    """Like time_candidates, but each candidate is timed where a batch runs it: a
+    batch plan of `copies` copies of the request (own outputs each), replayed as a
+    graph; the time per product is the replay time divided by `copies`.  Merged
+    passes hide launch and tail costs that dominate single products, so these
+    times rank candidates for batch plans."""
+    import torch
+    out = []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for r in reqs:
+        cands = B.ss_candidates(r.len_g, r.g_limbs, r.len_h, r.h_limbs)
+        n_out = (r.len_g + r.len_h - 1) * r.out_limbs
+        outs = [torch.empty(n_out, dtype=torch.int32, device=device) for _ in range(copies)]
+        ms = []
+        for c in cands:
+            arr = (B.ZXRequest * copies)()
+            for i in range(copies):
+                q = B.ZXRequest(r.g, r.len_g, r.g_limbs, r.h, r.len_h, r.h_limbs, outs[i].data_ptr(), r.out_limbs)
+                q.params = c
+                arr[i] = q
+            plan = B.BatchPlan(arr)
+            ws = torch.empty(max(1, plan.workspace), dtype=torch.uint8, device=device)
+            plan.execute(ws, use_graph=True)  # direct run + capture
+            plan.execute(ws, use_graph=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(replays):
+                plan.execute(ws, use_graph=True)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1) / (replays * copies))
+            plan.close()
+            del ws
+        best = min(range(len(ms)), key=lambda i: (ms[i], i))
+        out.append((cands, ms, best))
+        del outs
+    return out
+
+
 def training_rows(reqs, timings):
     """Features (rows x SS_FEATURES) and targets from time_candidates output.  A
     target is log(ms) less the mean log(ms) over the request's candidates: only
