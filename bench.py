@@ -407,8 +407,9 @@ def split_sweep(T, torch, bits=8000, lo=512, hi=16384, step=1.05, reps=3):
         ow = (32 * 2 * limbs + (ln - 1).bit_length() + 31) // 32
         res = {}
         outs = []
-        for name, top, pad in (("bailey", 0, 0), ("dc", T.SPLIT_DC, 0), ("padded", 0, 1)):
-            p = T.SSParams(0, 0, T.Split(top, 0), 1, pad)
+        for name, top, pad, zexp in (("bailey", 0, 0, 0), ("dc", T.SPLIT_DC, 0, 0), ("padded", 0, 1, 0),
+                                     ("padded_twisted", 0, 1, 3 * 16384 // 2)):
+            p = T.SSParams(0, 0, T.Split(top, 0), 1, pad, zexp)
             ws = torch.empty(T.zx_mul_ss_workspace(ln, limbs, ln, limbs, p), dtype=torch.uint8, device="cuda")
             o = torch.empty((2 * ln - 1, ow), dtype=torch.int32, device="cuda")
             T.zx_mul_ss_timed(dg, dh, o, p, ws=ws)
@@ -417,8 +418,8 @@ def split_sweep(T, torch, bits=8000, lo=512, hi=16384, step=1.05, reps=3):
             res[name] = t
             outs.append(o)
             del ws
-        same = bool(torch.equal(outs[0], outs[1])) and bool(torch.equal(outs[0], outs[2]))
-        b, d, w = res["bailey"], res["dc"], res["padded"]
+        same = all(bool(torch.equal(outs[0], o)) for o in outs[1:])
+        b, d, w, wt = res["bailey"], res["dc"], res["padded"], res["padded_twisted"]
 
         def tr(t):
             return t["tft_g_ms"] + t["tft_h_ms"] + t["itft_ms"]
@@ -428,6 +429,7 @@ def split_sweep(T, torch, bits=8000, lo=512, hi=16384, step=1.05, reps=3):
                      "dc_transform_ms": round(tr(d), 4), "bailey_launches": b["leaf_launches"],
                      "dc_launches": d["leaf_launches"], "padded_ms": round(w["total_ms"], 4),
                      "padded_transform_ms": round(tr(w), 4), "padded_launches": w["leaf_launches"],
+                     "padded_twisted_ms": round(wt["total_ms"], 4), "padded_twisted_transform_ms": round(tr(wt), 4),
                      "same_output": same})
         _progress("split sweep len %d: bailey %.3f ms, dc %.3f ms, padded %.3f ms, same %s"
                   % (ln, b["total_ms"], d["total_ms"], w["total_ms"], same))
@@ -445,7 +447,10 @@ def split_sweep(T, torch, bits=8000, lo=512, hi=16384, step=1.05, reps=3):
             "product_time_ratio_dc_over_bailey": spread("dc_ms", "bailey_ms"),
             "transform_time_ratio_dc_over_bailey": spread("dc_transform_ms", "bailey_transform_ms"),
             "product_time_ratio_padded_over_bailey": spread("padded_ms", "bailey_ms"),
-            "transform_time_ratio_padded_over_bailey": spread("padded_transform_ms", "bailey_transform_ms")}
+            "transform_time_ratio_padded_over_bailey": spread("padded_transform_ms", "bailey_transform_ms"),
+            "product_time_ratio_padded_twisted_over_bailey": spread("padded_twisted_ms", "bailey_ms"),
+            "transform_time_ratio_padded_twisted_over_bailey": spread("padded_twisted_transform_ms",
+                                                                      "bailey_transform_ms")}
 
 
 def main():
