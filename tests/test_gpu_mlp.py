@@ -114,6 +114,14 @@ def test_exhaustive_timing_first_minimum():
     assert best == int(np.argmin(np.array(ms)))
 
 
+def test_batch_context_timing_first_minimum():
+    keep, reqs = _requests([5, 6], scale=8)
+    note("batch-context candidate timing on two requests")
+    for cands, ms, best in tuning.time_candidates_in_batch(reqs, copies=2, replays=1):
+        assert len(ms) == len(cands) and all(v > 0 for v in ms)
+        assert best == int(np.argmin(np.array(ms)))
+
+
 def test_model_regret_and_gain():
     keep_tr, train = _requests(range(1000, 1032), scale=2)
     keep_te, test = _requests(range(2000, 2012), scale=2)
