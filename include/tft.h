@@ -119,6 +119,16 @@ int tft_forward(const tft_ring *ring, uint32_t l, uint64_t s, uint64_t z, uint64
 int itft_inverse(const tft_ring *ring, uint32_t l, uint64_t s, uint64_t z, uint64_t n, uint32_t f, void *x,
                  void *stream);
 
+/* Self-test of the transform kernel's arithmetic for FERMAT rings with
+ * N = 8192 .. 65536: runs `ncases` single base cases of Alg. 1 / Alg. 2 (the
+ * L = 2 cases, Sect. 3 and Sect. 4), one wavefront each, as the leaf kernel
+ * runs them.  `cases` and `out` are device arrays of records of 4 + 2W uint32
+ * (W = N/32): opcode (the numbering of tft_plan_export), exponent e of
+ * zeta = 2^e (mod 2N), top word of x0, top word of x1, then the W limbs of x0
+ * and of x1 (cells as in the cell-array layout, canonical).  `out` receives
+ * the records after the base case.  TFT_E_UNSUPPORTED for other rings. */
+int tft_debug_base_cases(const tft_ring *ring, uint32_t ncases, const void *cases, void *out, void *stream);
+
 /* Pointwise products (Sect. 2: u_hat_i = g_hat_i h_hat_i, 0 <= i < n):
  *   c_i = a_i * b_i * 2^(-scale_log2) in R for 0 <= i < n.
  * a, b, c are cell arrays of capacity `cap` (n <= cap); c may alias a or b.

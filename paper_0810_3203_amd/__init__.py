@@ -18,6 +18,7 @@ from ._binding import (  # noqa: F401
     Split,
     TFTError,
     array_bytes,
+    debug_base_cases,
     elem_bytes,
     fermat_ring,
     itft_inverse,

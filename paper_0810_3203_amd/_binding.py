@@ -100,6 +100,8 @@ def lib():
         L.tft_forward.restype = I
         L.itft_inverse.argtypes = [RP, U32, U64, U64, U64, U32, P, P]
         L.itft_inverse.restype = I
+        L.tft_debug_base_cases.argtypes = [RP, U32, P, P, P]
+        L.tft_debug_base_cases.restype = I
         L.pointwise_mul.argtypes = [RP, U64, P, P, P, U64, U32, P]
         L.pointwise_mul.restype = I
         L.zx_mul_ss_workspace.argtypes = [U64, U32, U64, U32, ctypes.POINTER(SSParams), ctypes.POINTER(U64)]
@@ -212,6 +214,12 @@ def tft_forward(ring, l, s, z, n, x, stream=None):
 def itft_inverse(ring, l, s, z, n, f, x, stream=None):
     """In-place ITFT(2^l, theta^s, z, n, f) on cell array x."""
     _check(lib().itft_inverse(ctypes.byref(ring), l, s, z, n, f, _ptr(x), _stream(stream)), "itft_inverse")
+
+
+def debug_base_cases(ring, ncases, cases, out, stream=None):
+    """Runs single base cases on the device (records: see tft_debug_base_cases in tft.h)."""
+    _check(lib().tft_debug_base_cases(ctypes.byref(ring), ncases, _ptr(cases), _ptr(out), _stream(stream)),
+           "tft_debug_base_cases")
 
 
 def pointwise_mul(ring, n, a, b, c, cap, scale_log2=0, stream=None):

@@ -393,6 +393,16 @@ int itft_inverse(const tft_ring *ring, uint32_t l, uint64_t s, uint64_t z, uint6
     return plan_run(cached_plan(ring, 1, l, s, z, n, f, nullptr), x, static_cast<hipStream_t>(stream));
 }
 
+int tft_debug_base_cases(const tft_ring *ring, uint32_t ncases, const void *cases, void *out, void *stream) {
+    int st = check_ring(ring);
+    if (st) return st;
+    if (ring->kind != TFT_RING_FERMAT || ring->N < 8192 || ring->N > 65536) return TFT_E_UNSUPPORTED;
+    if (!cases || !out) return TFT_E_ARG;
+    return hip_status(launch_base_case_probe(ring->N / 32, ncases, static_cast<const uint32_t *>(cases),
+                                             static_cast<uint32_t *>(out), static_cast<hipStream_t>(stream)),
+                      "base case probe");
+}
+
 int pointwise_mul(const tft_ring *ring, uint64_t n, const void *a, const void *b, void *c, uint64_t cap,
                   uint32_t scale_log2, void *stream) {
     int st = check_ring(ring);

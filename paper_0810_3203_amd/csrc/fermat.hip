@@ -431,6 +431,9 @@ hipError_t launch_fermat_leaf(uint32_t W, uint32_t nwaves, uint32_t njobs, uint3
                               uint32_t job_offset, const LeafProg *progs, const LeafStep *steps, const LeafOp *ops,
                               uint32_t *x, uint64_t cap, uint32_t ord_mask, uint32_t opmask, bool transposed,
                               hipStream_t st) {
+    if (fermat_leaf2_supported(W))
+        return launch_fermat_leaf2(W, njobs, lds_cells, jobs, job_offset, progs, steps, ops, x, cap, ord_mask, opmask,
+                                   transposed, st);
     return transposed ? launch_fermat_leaf_trans(W, nwaves, njobs, lds_cells, jobs, job_offset, progs, steps, ops, x,
                                                  cap, ord_mask, opmask, st)
                       : launch_fermat_leaf_plain(W, nwaves, njobs, lds_cells, jobs, job_offset, progs, steps, ops, x,

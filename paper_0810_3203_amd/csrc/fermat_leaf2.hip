@@ -1,0 +1,122 @@
+// Instantiations and launcher of the persistent leaf executor (fermat_leaf2.hpp)
+// for elements of 256 to 2048 limbs, both global cell layouts.
+#include "fermat_leaf2.hpp"
+
+namespace tft {
+
+namespace {
+
+constexpr uint32_t kLds = 160u * 1024u;
+
+uint32_t device_cus() {
+    static int cache[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cache[dev]) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+        cache[dev] = cus;
+    }
+    return (uint32_t)cache[dev];
+}
+
+template <int C, bool TR>
+hipError_t leaf2_launch(uint32_t njobs, uint32_t lds_cells, const Job *jobs, uint32_t job_offset,
+                        const LeafProg *progs, const LeafStep *steps, const LeafOp *ops, uint32_t *x, uint64_t cap,
+                        uint32_t ord_mask, hipStream_t st) {
+    constexpr uint32_t W = 64u * C;
+    if (lds_cells == 0u || lds_cells * (W / 4u) > (uint32_t)lf2::kQuadsPerThread * lf2::kThreads || lds_cells > W)
+        return hipErrorInvalidValue;
+    const size_t lds = (size_t)lf2::lds_dwords(W, lds_cells) * 4u;
+    if (lds > kLds) return hipErrorInvalidValue;
+    auto kern = &lf2::fermat_leaf2_kernel<C, TR>;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const uint32_t grid = njobs < device_cus() ? njobs : device_cus();
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(lf2::kThreads), lds, st, jobs, progs, steps, ops, x, cap, ord_mask,
+                       job_offset, njobs);
+    return hipGetLastError();
+}
+
+// One base case per workgroup of one wave: record c holds the opcode, the
+// exponent, the two top words and the two cells (plain limb order).
+template <int C>
+__global__ void __launch_bounds__(64) base_case_probe_kernel(const uint32_t *__restrict__ in,
+                                                              uint32_t *__restrict__ out, uint32_t ncases) {
+    constexpr uint32_t W = 64u * C, REC = 4u + 2u * W;
+    extern __shared__ uint32_t sm[];
+    const uint32_t c = blockIdx.x;
+    if (c >= ncases) return;
+    const uint32_t *r = in + (size_t)c * REC;
+    const uint32_t l = threadIdx.x;
+    for (uint32_t k = l; k < W; k += 64u) {
+        sm[lf2::cell_base(W, 0) + lf2::limb_pos(C, k)] = r[4 + k];
+        sm[lf2::cell_base(W, 1) + lf2::limb_pos(C, k)] = r[4 + W + k];
+    }
+    if (l < 2u) sm[l] = r[2 + l];
+    __syncthreads();
+    const lf2::Big<C> ar;
+    const LeafOp o{(r[0] & 15u) | (0u << 4) | (1u << 18), 0u};
+    lf2::base_case<C>(ar, sm, o, r[1], 64u * W - 1u);
+    __syncthreads();
+    uint32_t *w = out + (size_t)c * REC;
+    for (uint32_t k = l; k < W; k += 64u) {
+        w[4 + k] = sm[lf2::cell_base(W, 0) + lf2::limb_pos(C, k)];
+        w[4 + W + k] = sm[lf2::cell_base(W, 1) + lf2::limb_pos(C, k)];
+    }
+    if (l < 2u) {
+        w[2 + l] = sm[l];
+        w[l] = r[l];
+    }
+}
+
+template <int C>
+hipError_t probe_launch(uint32_t ncases, const uint32_t *in, uint32_t *out, hipStream_t st) {
+    constexpr uint32_t W = 64u * C;
+    hipLaunchKernelGGL(base_case_probe_kernel<C>, dim3(ncases), dim3(64), lf2::lds_dwords(W, 2) * 4u, st, in, out,
+                       ncases);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_base_case_probe(uint32_t W, uint32_t ncases, const uint32_t *in, uint32_t *out, hipStream_t st) {
+    if (ncases == 0) return hipSuccess;
+    switch (W) {
+        case 256: return probe_launch<4>(ncases, in, out, st);
+        case 512: return probe_launch<8>(ncases, in, out, st);
+        case 1024: return probe_launch<16>(ncases, in, out, st);
+        case 2048: return probe_launch<32>(ncases, in, out, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+bool fermat_leaf2_supported(uint32_t W) { return W >= 256u && W <= 2048u && (W & (W - 1u)) == 0u; }
+
+hipError_t launch_fermat_leaf2(uint32_t W, uint32_t njobs, uint32_t lds_cells, const Job *jobs, uint32_t job_offset,
+                               const LeafProg *progs, const LeafStep *steps, const LeafOp *ops, uint32_t *x,
+                               uint64_t cap, uint32_t ord_mask, uint32_t opmask, bool transposed, hipStream_t st) {
+    (void)opmask;  // one kernel runs every base case
+    if (njobs == 0) return hipSuccess;
+#define TFT_LEAF2_CASE(CC)                                                                                        \
+    case 64 * CC:                                                                                                 \
+        return transposed ? leaf2_launch<CC, true>(njobs, lds_cells, jobs, job_offset, progs, steps, ops, x, cap, \
+                                                   ord_mask, st)                                                  \
+                          : leaf2_launch<CC, false>(njobs, lds_cells, jobs, job_offset, progs, steps, ops, x, cap, \
+                                                    ord_mask, st);
+    switch (W) {
+        TFT_LEAF2_CASE(4)
+        TFT_LEAF2_CASE(8)
+        TFT_LEAF2_CASE(16)
+        TFT_LEAF2_CASE(32)
+        default: return hipErrorInvalidValue;
+    }
+#undef TFT_LEAF2_CASE
+}
+
+}  // namespace tft

@@ -27,6 +27,17 @@ hipError_t launch_fermat_leaf_trans(uint32_t W, uint32_t nwaves, uint32_t njobs,
                                     const LeafOp *ops, uint32_t *x, uint64_t cap, uint32_t ord_mask, uint32_t opmask,
                                     hipStream_t st);
 
+// Persistent leaf executor for W = 256 .. 2048 (fermat_leaf2.hpp): 512 threads
+// per workgroup, one workgroup per compute unit, the next job's cells loaded
+// into registers while the current job runs.
+bool fermat_leaf2_supported(uint32_t W);
+hipError_t launch_fermat_leaf2(uint32_t W, uint32_t njobs, uint32_t lds_cells, const Job *jobs, uint32_t job_offset,
+                               const LeafProg *progs, const LeafStep *steps, const LeafOp *ops, uint32_t *x,
+                               uint64_t cap, uint32_t ord_mask, uint32_t opmask, bool transposed, hipStream_t st);
+
+// Single base cases of the persistent executor, one wave each (self-test of its arithmetic).
+hipError_t launch_base_case_probe(uint32_t W, uint32_t ncases, const uint32_t *in, uint32_t *out, hipStream_t st);
+
 // c_i = a_i b_i 2^scale_e (scale_e = -scale_log2 mod 2N) for i < n, cell arrays of capacity cap.
 hipError_t launch_fermat_pointwise(uint32_t W, uint64_t n, const uint32_t *a, const uint32_t *b, uint32_t *c,
                                    uint64_t cap, uint32_t scale_e, bool transposed, hipStream_t st);

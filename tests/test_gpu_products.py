@@ -168,11 +168,28 @@ def test_zmx_small_full(coracle, lg, lh, log2K, m):
 
 
 def test_zmx_case4_full_size(coracle):
+    """The 500,000 x 500,000 product (K = 1024, 977 pieces of 512 per operand).
+
+    Whole output: sum_k u_k r^k = g(r) h(r) (mod m) at two random points r; the
+    identity holds in Z/mZ for the product reduced coefficient by coefficient, so
+    a wrong piece (about 1024 outputs) changes the sum unless r is a root of the
+    error polynomial.  Coefficients: every piece boundary 512k - 1, 512k, 512k + 1
+    (the overlap-add of Sect. 5.2 joins pieces there), the ends, and random ones,
+    each by its schoolbook sum."""
     m, g, h = wl.zmx_operands()
     note("zmx_mul_nussbaumer case 4 (500000 x 500000, K = 1024)")
     got = _zmx_gpu(g, h, m, 10)
+    assert got.shape == (999999,)
+    assert int(got.max()) < m
     rng = random.Random(4)
+    for _ in range(2):
+        r = rng.randrange(2, m - 1)
+        lhs = coracle.fingerprint64(got, m, r)
+        rhs = coracle.fingerprint64(g, m, r) * coracle.fingerprint64(h, m, r) % m
+        assert lhs == rhs, "fingerprint mod m differs"
     ks = list(range(4)) + list(range(999995, 999999)) + [rng.randrange(999999) for _ in range(120)]
-    ks += [511, 512, 513, 1023, 1024, 499999, 500000]  # piece boundaries
+    ks += [512 * k + d for k in range(1, 1954) for d in (-1, 0, 1) if 0 <= 512 * k + d < 999999]
+    ks = sorted(set(ks))
     expect = coracle.zmx_coeffs(g, h, m, ks)
-    assert np.array_equal(got[ks], expect)
+    bad = [k for k, e in zip(ks, expect) if int(got[k]) != int(e)]
+    assert not bad, "coefficients differ at %s" % bad[:8]

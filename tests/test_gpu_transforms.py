@@ -303,3 +303,56 @@ def test_nega_pointwise(K):
             T.pointwise_mul(T.nega_ring(K, m), n, da, db, dc, cap, scale)
             torch.cuda.synchronize()
             assert nega_from_device(dc, K, n) == O.pointwise(ring, a[:n], b[:n], scale)
+
+
+def _times_pow2_mod(a, k, m):
+    """a * 2^k mod m for uint64 arrays with entries < m < 2^62 (repeated doubling, no overflow)."""
+    a = np.array(a, dtype=np.uint64)
+    mm = np.uint64(m)
+    for _ in range(k):
+        a = a * np.uint64(2)
+        a = np.where(a >= mm, a - mm, a)
+    return a
+
+
+@pytest.mark.parametrize("s", [0, 1537])
+def test_nega_transforms_case4_shape(coracle, s):
+    """TFT and ITFT at the shape of the Schoenhage-Nussbaumer product (Sect. 5.2):
+    K = 1024, L = 2^11 (several leaf passes), z = 977 pieces, n = 1953, the
+    product's 62-bit modulus.  Every TFT output is compared with eq. (1) in the C
+    oracle; the ITFT is checked by construction for (z, n, f) = (n, n, 0), the
+    product's inverse, and (n, n - 1, 1)."""
+    from synth import workloads as wl
+    m = wl.zmx_operands(len_g=1, len_h=1)[0]
+    K, l, z, n = 1024, 11, 977, 1953
+    L = 1 << l
+    rng = np.random.default_rng(4 + s)
+    a = (rng.integers(0, 1 << 62, size=(L, K), dtype=np.uint64) % np.uint64(m)).astype(np.uint64)
+    a[0] = m - 1
+    a[1, ::2] = 0
+    ring = T.nega_ring(K, m)
+    note("nega tft K=%d l=%d z=%d n=%d s=%d (product shape)" % (K, l, z, n, s))
+    x = torch.from_numpy(a.reshape(-1).view(np.int64)).cuda()
+    T.tft_forward(ring, l, s, z, n, x)
+    torch.cuda.synchronize()
+    got = x.cpu().numpy().view(np.uint64).reshape(L, K)[:n]
+    expect = coracle.nega_dft_sampled(K, m, L, s, a[:z], list(range(n)))
+    bad = np.nonzero(np.any(got != expect, axis=1))[0]
+    assert len(bad) == 0, "TFT outputs differ at %s" % bad[:8].tolist()
+
+    b = (rng.integers(0, 1 << 62, size=(n, K), dtype=np.uint64) % np.uint64(m)).astype(np.uint64)
+    ahat = coracle.nega_dft_sampled(K, m, L, s, b, list(range(n)))
+    Lb = _times_pow2_mod(b, l, m)
+    for zz, nn, f in ((n, n, 0), (n, n - 1, 1)):
+        note("nega itft K=%d l=%d z=%d n=%d f=%d s=%d (product shape)" % (K, l, zz, nn, f, s))
+        fill = (rng.integers(0, 1 << 62, size=(L, K), dtype=np.uint64) % np.uint64(m)).astype(np.uint64)
+        fill[:nn] = ahat[:nn]
+        fill[nn:zz] = Lb[nn:zz]
+        x = torch.from_numpy(fill.reshape(-1).view(np.int64)).cuda()
+        T.itft_inverse(ring, l, s, zz, nn, f, x)
+        torch.cuda.synchronize()
+        got = x.cpu().numpy().view(np.uint64).reshape(L, K)
+        bad = np.nonzero(np.any(got[:nn] != Lb[:nn], axis=1))[0]
+        assert len(bad) == 0, "ITFT outputs differ at %s" % bad[:8].tolist()
+        if f:
+            assert np.array_equal(got[nn], ahat[nn]), "ITFT f output differs"

@@ -1,0 +1,56 @@
+"""Host run of the leaf executor's arithmetic under a lockstep wave emulation.
+
+tests/native/leaf2_ops_emu.cpp compiles the kernel's wave-level code
+(paper_0810_3203_amd/csrc/fermat_leaf2_ops.hpp) for the host, with 64 threads
+as the lanes of one wavefront, and runs every base case of Alg. 1 and Alg. 2
+(L = 2) on two cells for elements of 256 to 2048 limbs: random operands, 0,
+1, 2^N, 2^N - 1, operands filling one half, whole lane chunks of zeros or
+ones, single limbs and long runs of ones, with twist exponents at every
+rotation boundary.  Each result is compared here, with Python integers, with
+the base case's definition in Z/(2^N+1) (tests/base_case_defs.py).
+
+The emulation reproduces the source's meaning, not the compiler's output: a
+wrong carry that the compiler introduced on the device (it once merged the
+last limb of a dropped-carry chain into the next chain) shows up only in
+tests/test_gpu_base_cases.py, which runs the same cases on the GPU.
+"""
+
+import os
+import subprocess
+
+import pytest
+
+from tests.base_case_defs import expect
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def emu_exe(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("emu") / "leaf2_ops_emu")
+    subprocess.check_call(["g++", "-O2", "-std=c++20", "-pthread", "-I",
+                           os.path.join(ROOT, "paper_0810_3203_amd", "csrc"),
+                           os.path.join(ROOT, "tests", "native", "leaf2_ops_emu.cpp"), "-o", exe])
+    return exe
+
+
+@pytest.mark.parametrize("C,cases,seed", [(4, 300, 1), (8, 200, 2), (16, 120, 3), (32, 80, 4)])
+def test_base_cases_emulated(emu_exe, C, cases, seed):
+    r = subprocess.run([emu_exe, str(C), str(cases), str(seed)], capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr
+    lines = r.stdout.strip().splitlines()
+    assert len(lines) == cases
+    bad = []
+    for ln in lines:
+        f = ln.split()
+        c, code, s = int(f[0]), int(f[1]), int(f[2])
+        N = 32 * 64 * c
+        x0 = int(f[3], 16) + (int(f[4]) << N)
+        x1 = int(f[5], 16) + (int(f[6]) << N)
+        y0 = int(f[7], 16) + (int(f[8]) << N)
+        y1 = int(f[9], 16) + (int(f[10]) << N)
+        e0, e1 = expect(code, N, s, x0, x1)
+        canon = all(v <= (1 << N) and (v >> N == 0 or v == 1 << N) for v in (y0, y1))
+        if y0 != e0 or (e1 is not None and y1 != e1) or not canon:
+            bad.append((code, s, hex(x0)[:20], hex(x1)[:20]))
+    assert not bad, "%d of %d base cases wrong, first: %s" % (len(bad), cases, bad[:5])
