@@ -17,9 +17,14 @@
  *   - On any argument error nothing is launched and nothing is written.
  *   - zeta is passed as an exponent s: zeta = theta^s (Sect. 6), with theta
  *     the ring's shift unit (2 in Z/(2^N+1), y in (Z/mZ)[y]/(y^K+1)).
- *   - Reentrant for distinct buffers and streams.  The first call with a new
- *     shape builds and uploads a plan (host work plus hipMalloc of a few KB of
- *     descriptors); later calls with that shape allocate nothing.
+ *   - Reentrant for distinct buffers and streams.  Executing a transform,
+ *     a pointwise product or a created plan allocates no device memory:
+ *     tft_forward / itft_inverse copy their descriptors into a caller
+ *     workspace (tft_transform_workspace gives its size), explicit and batch
+ *     plans upload theirs when they are created.  The products zx_mul_ss and
+ *     zmx_mul_nussbaumer build, upload and cache the plans of a new shape on
+ *     its first call (host work plus hipMalloc of a few KB); later calls with
+ *     that shape allocate nothing.
  *
  * Cell arrays (the array x_0..x_{L-1} of Sect. 2, "Algorithms 1 and 2 operate
  * on an array x_0, ..., x_{L-1}")
@@ -100,24 +105,40 @@ uint64_t tft_elem_bytes(const tft_ring *ring);
 /* Bytes of a cell array with `cells` cells (layout above). 0 if unsupported. */
 uint64_t tft_array_bytes(const tft_ring *ring, uint64_t cells);
 
+/* Device workspace bytes that tft_forward (direction 0) or itft_inverse
+ * (direction 1) needs for this shape: the transform's pass descriptors (jobs,
+ * leaf programs, base cases), a few KB.  Host work only; f is ignored for the
+ * TFT.  Same argument errors as the transforms. */
+int tft_transform_workspace(const tft_ring *ring, uint32_t direction, uint32_t l, uint64_t s, uint64_t z, uint64_t n,
+                            uint32_t f, uint64_t *bytes);
+
 /* TFT(L, zeta, z, n) of Sect. 2 computed in place by Alg. 1 (Sect. 3).
  *   l       transform length L = 2^l, 1 <= l <= 24; L must divide ord(theta).
  *   s       zeta = theta^s (any s; taken mod ord(theta)).
  *   z, n    1 <= z <= L, 1 <= n <= L.
  *   x       cell array of capacity L.  Cells [0, z) hold a_0..a_{z-1}; cells
  *           >= z are never read (a_i = 0 there) and may hold anything.
+ *   ws      device workspace of ws_bytes >= tft_transform_workspace(...)
+ *           bytes, 256-byte aligned; TFT_E_WORKSPACE if NULL or too small.
+ *           The descriptors are copied into it on `stream` (an asynchronous
+ *           host-to-device copy from library-owned host memory), so it must
+ *           not be in use by another call until this one has finished.
  * On return cells [0, n) hold a_hat_0..a_hat_{n-1} of eq. (1); all other
- * cells are clobbered (Sect. 2: every cell may serve as scratch). */
-int tft_forward(const tft_ring *ring, uint32_t l, uint64_t s, uint64_t z, uint64_t n, void *x, void *stream);
+ * cells are clobbered (Sect. 2: every cell may serve as scratch).  Allocates
+ * no device memory; the launch sequence may be captured into a hipGraph. */
+int tft_forward(const tft_ring *ring, uint32_t l, uint64_t s, uint64_t z, uint64_t n, void *x, void *ws,
+                uint64_t ws_bytes, void *stream);
 
 /* ITFT(L, zeta, z, n, f) of Sect. 2 computed in place by Alg. 2 (Sect. 4).
  *   f in {0, 1}; 1 <= z <= L; z >= n; 1 <= n + f <= L.
  *   x       cell array of capacity L: cells [0, n) hold a_hat_0..a_hat_{n-1},
  *           cells [n, z) hold L*a_n..L*a_{z-1}; cells >= z are never read.
+ *   ws      device workspace as for tft_forward (direction 1).
  * On return cells [0, n) hold L*a_0..L*a_{n-1} (NOT divided by L) and, if
- * f = 1, cell n holds a_hat_n; every other cell is clobbered. */
-int itft_inverse(const tft_ring *ring, uint32_t l, uint64_t s, uint64_t z, uint64_t n, uint32_t f, void *x,
-                 void *stream);
+ * f = 1, cell n holds a_hat_n; every other cell is clobbered.  Allocates no
+ * device memory. */
+int itft_inverse(const tft_ring *ring, uint32_t l, uint64_t s, uint64_t z, uint64_t n, uint32_t f, void *x, void *ws,
+                 uint64_t ws_bytes, void *stream);
 
 /* Self-test of the transform kernel's arithmetic for FERMAT rings with
  * N = 8192 .. 65536: runs `ncases` single base cases of Alg. 1 / Alg. 2 (the
@@ -232,17 +253,34 @@ typedef struct {
 
 typedef struct tft_batch_plan tft_batch_plan;
 
-/* Plan `count` products for execution together (host work only).  Requests are
- * grouped by ring size; in each group pass p of every TFT (resp. ITFT) is one
- * kernel launch, and the pointwise products are one launch.  Requests whose
- * arguments are invalid are skipped and reported by tft_batch_plan_status.
+/* How a batch plan picks each request's parameters (k, N, l, split, padding):
+ *   TFT_POLICY_GIVEN  the request's params as given (all zero = the default
+ *                     rule of tft_ss_default_params);
+ *   TFT_POLICY_RULE   the default rule for every request, params ignored;
+ *   TFT_POLICY_MODEL  the candidate (tft_ss_candidates) of smallest time
+ *                     predicted by a cost model (tft_mlp_choose_ss). */
+enum { TFT_POLICY_GIVEN = 0, TFT_POLICY_RULE = 1, TFT_POLICY_MODEL = 2 };
+
+/* Plan `count` products for execution together.  Requests are grouped by ring
+ * size; in each group pass p of every TFT (resp. ITFT) is one kernel launch,
+ * and the pointwise products are one launch.  Requests whose arguments are
+ * invalid are skipped and reported by tft_batch_plan_status.
  * max_workspace (bytes, 0 = no limit) splits the requests into consecutive
  * chunks run one after another in the same workspace; a request whose own
  * workspace, rounded up to a multiple of 256 bytes, exceeds the limit is
- * skipped with TFT_E_WORKSPACE.  The request pointers are used by every
- * execution of the plan. */
-int tft_batch_plan_create(const tft_zx_request *reqs, uint32_t count, uint64_t max_workspace,
-                          tft_batch_plan **plan);
+ * skipped with TFT_E_WORKSPACE.  policy is one of TFT_POLICY_*; `model` is
+ * required for TFT_POLICY_MODEL and ignored otherwise (TFT_E_ARG).  The
+ * request array is copied; its g, h and out pointers are used by every
+ * execution of the plan.  With a device present the plan's descriptors are
+ * uploaded to the current device (hipMalloc) and a capture stream is made
+ * here, so that executions allocate nothing; without one the plan is host
+ * data only. */
+int tft_batch_plan_create(const tft_zx_request *reqs, uint32_t count, uint64_t max_workspace, int policy,
+                          struct tft_mlp *model, tft_batch_plan **plan);
+
+/* The parameters each request was planned with (count entries), after the
+ * policy; entries of skipped requests are as the policy left them. */
+int tft_batch_plan_params(const tft_batch_plan *plan, tft_ss_params *params);
 
 /* Device workspace bytes the plan needs. */
 uint64_t tft_batch_plan_workspace(const tft_batch_plan *plan);
@@ -253,11 +291,12 @@ int tft_batch_plan_status(const tft_batch_plan *plan, int *status);
 /* Kernel launches of one execution. */
 uint32_t tft_batch_plan_launches(const tft_batch_plan *plan);
 
-/* Run every planned product on `stream`.  use_graph = 0: the launches are
- * issued directly.  use_graph = 1: the first call (and any call with another
- * workspace pointer) runs the launches and captures them into a hipGraph;
- * later calls replay the graph.  The first call uploads the plan's descriptors
- * (hipMalloc); nothing is allocated afterwards. */
+/* Run every planned product on `stream`, on the device the plan was created
+ * on (TFT_E_ARG otherwise).  use_graph = 0: the launches are issued directly.
+ * use_graph = 1: the first call (and any call with another workspace pointer)
+ * runs the launches and captures them on the plan's own stream into a
+ * hipGraph; later calls replay the graph.  No call allocates device memory
+ * (the runtime's graph instantiation aside). */
 int tft_batch_plan_execute(tft_batch_plan *plan, void *ws, uint64_t ws_bytes, int use_graph, void *stream);
 
 /* Free a batch plan (host data, device descriptors, graph).  NULL is ignored. */
@@ -334,13 +373,16 @@ int tft_mlp_choose_ss(tft_mlp *mlp, tft_zx_request *reqs, uint32_t count, void *
 
 typedef struct tft_plan tft_plan;
 
-/* Build the pass schedule of one transform (direction 0 = TFT, 1 = ITFT) on
- * the host.  Pure host work: needs no GPU.  f is ignored for the TFT. */
+/* Build the pass schedule of one transform (direction 0 = TFT, 1 = ITFT) and
+ * upload its descriptors to the current device (hipMalloc of a few KB).  With
+ * no device present the plan is built on the host only (for tft_plan_export
+ * and tft_plan_base_cases).  f is ignored for the TFT. */
 int tft_plan_create(const tft_ring *ring, uint32_t direction, uint32_t l, uint64_t s, uint64_t z, uint64_t n,
                     uint32_t f, const tft_split *split, tft_plan **plan);
 
-/* Run a plan in place on cell array x (capacity 2^l) on `stream`.  The first
- * execution uploads the plan's descriptors. */
+/* Run a plan in place on cell array x (capacity 2^l) on `stream`.  Allocates
+ * nothing on the device the plan was created on; the first execution on
+ * another device uploads the descriptors there. */
 int tft_plan_execute(tft_plan *plan, void *x, void *stream);
 
 /* Free a plan (host and device descriptors).  NULL is ignored. */

@@ -10,6 +10,9 @@ from ._binding import (  # noqa: F401
     FERMAT,
     MLP,
     NEGA,
+    POLICY_GIVEN,
+    POLICY_MODEL,
+    POLICY_RULE,
     SPLIT_DC,
     SS_FEATURES,
     BatchPlan,
@@ -34,6 +37,7 @@ from ._binding import (  # noqa: F401
     ss_time,
     status_string,
     tft_forward,
+    transform_workspace,
     zmx_mul_nussbaumer,
     zmx_mul_nussbaumer_workspace,
     zx_mul_ss,
@@ -48,5 +52,5 @@ __all__ = [
     "itft_inverse", "lib", "lib_path", "nega_ring", "pointwise_mul", "ring_check", "status_string", "tft_forward",
     "zmx_mul_nussbaumer", "zmx_mul_nussbaumer_workspace", "zx_mul_ss", "zx_mul_ss_timed", "zx_mul_ss_workspace",
     "BatchPlan", "MLP", "SPLIT_DC", "SS_FEATURES", "ZXRequest", "requests_array", "ss_candidates", "ss_default_params",
-    "ss_features", "ss_time", "zx_request",
+    "ss_features", "ss_time", "zx_request", "POLICY_GIVEN", "POLICY_RULE", "POLICY_MODEL", "transform_workspace",
 ]

@@ -35,6 +35,7 @@ class Ring(ctypes.Structure):
 
 # top_l1 value selecting L1 = 2 at every level above the leaf (TFT_SPLIT_DC)
 SPLIT_DC = 0xFFFFFFFF
+POLICY_GIVEN, POLICY_RULE, POLICY_MODEL = 0, 1, 2
 
 
 class Split(ctypes.Structure):
@@ -96,9 +97,11 @@ def lib():
         L.tft_elem_bytes.restype = U64
         L.tft_array_bytes.argtypes = [RP, U64]
         L.tft_array_bytes.restype = U64
-        L.tft_forward.argtypes = [RP, U32, U64, U64, U64, P, P]
+        L.tft_transform_workspace.argtypes = [RP, U32, U32, U64, U64, U64, U32, ctypes.POINTER(U64)]
+        L.tft_transform_workspace.restype = I
+        L.tft_forward.argtypes = [RP, U32, U64, U64, U64, P, P, U64, P]
         L.tft_forward.restype = I
-        L.itft_inverse.argtypes = [RP, U32, U64, U64, U64, U32, P, P]
+        L.itft_inverse.argtypes = [RP, U32, U64, U64, U64, U32, P, P, U64, P]
         L.itft_inverse.restype = I
         L.tft_debug_base_cases.argtypes = [RP, U32, P, P, P]
         L.tft_debug_base_cases.restype = I
@@ -128,8 +131,10 @@ def lib():
         RQ = ctypes.POINTER(ZXRequest)
         SP = ctypes.POINTER(SSParams)
         FP = ctypes.POINTER(ctypes.c_float)
-        L.tft_batch_plan_create.argtypes = [RQ, U32, U64, ctypes.POINTER(P)]
+        L.tft_batch_plan_create.argtypes = [RQ, U32, U64, I, P, ctypes.POINTER(P)]
         L.tft_batch_plan_create.restype = I
+        L.tft_batch_plan_params.argtypes = [P, SP]
+        L.tft_batch_plan_params.restype = I
         L.tft_batch_plan_workspace.argtypes = [P]
         L.tft_batch_plan_workspace.restype = U64
         L.tft_batch_plan_status.argtypes = [P, ctypes.POINTER(I)]
@@ -206,14 +211,35 @@ def array_bytes(ring: Ring, cells: int) -> int:
     return lib().tft_array_bytes(ctypes.byref(ring), cells)
 
 
-def tft_forward(ring, l, s, z, n, x, stream=None):
-    """In-place TFT(2^l, theta^s, z, n) on cell array x (a device tensor of capacity 2^l)."""
-    _check(lib().tft_forward(ctypes.byref(ring), l, s, z, n, _ptr(x), _stream(stream)), "tft_forward")
+def transform_workspace(ring, direction, l, s, z, n, f=0) -> int:
+    """Device workspace bytes of tft_forward (direction 0) / itft_inverse (1)."""
+    b = ctypes.c_uint64(0)
+    _check(lib().tft_transform_workspace(ctypes.byref(ring), direction, l, s, z, n, f, ctypes.byref(b)),
+           "tft_transform_workspace")
+    return b.value
 
 
-def itft_inverse(ring, l, s, z, n, f, x, stream=None):
+def _transform_ws(ring, direction, l, s, z, n, f, x, ws):
+    if ws is None:
+        import torch
+        need = transform_workspace(ring, direction, l, s, z, n, f)
+        ws = torch.empty(need, dtype=torch.uint8, device=x.device)
+    return ws
+
+
+def tft_forward(ring, l, s, z, n, x, ws=None, stream=None):
+    """In-place TFT(2^l, theta^s, z, n) on cell array x (a device tensor of
+    capacity 2^l).  ws: device workspace (allocated here if None)."""
+    ws = _transform_ws(ring, 0, l, s, z, n, 0, x, ws)
+    _check(lib().tft_forward(ctypes.byref(ring), l, s, z, n, _ptr(x), _ptr(ws), ws.numel() * ws.element_size(),
+                             _stream(stream)), "tft_forward")
+
+
+def itft_inverse(ring, l, s, z, n, f, x, ws=None, stream=None):
     """In-place ITFT(2^l, theta^s, z, n, f) on cell array x."""
-    _check(lib().itft_inverse(ctypes.byref(ring), l, s, z, n, f, _ptr(x), _stream(stream)), "itft_inverse")
+    ws = _transform_ws(ring, 1, l, s, z, n, f, x, ws)
+    _check(lib().itft_inverse(ctypes.byref(ring), l, s, z, n, f, _ptr(x), _ptr(ws),
+                              ws.numel() * ws.element_size(), _stream(stream)), "itft_inverse")
 
 
 def debug_base_cases(ring, ncases, cases, out, stream=None):
@@ -352,12 +378,19 @@ def requests_array(reqs):
 class BatchPlan:
     """tft_batch_plan_*: many Z[x] products planned and run together."""
 
-    def __init__(self, reqs, max_workspace=0):
+    def __init__(self, reqs, max_workspace=0, policy=POLICY_GIVEN, model=None):
         self.count = len(reqs)
         self._reqs = reqs if isinstance(reqs, ctypes.Array) else requests_array(reqs)
         self._p = ctypes.c_void_p()
-        _check(lib().tft_batch_plan_create(self._reqs, self.count, max_workspace, ctypes.byref(self._p)),
+        _check(lib().tft_batch_plan_create(self._reqs, self.count, max_workspace, policy,
+                                           model._p if model is not None else None, ctypes.byref(self._p)),
                "tft_batch_plan_create")
+
+    def params(self):
+        """The SSParams each request was planned with."""
+        arr = (SSParams * max(1, self.count))()
+        _check(lib().tft_batch_plan_params(self._p, arr), "tft_batch_plan_params")
+        return list(arr)[:self.count]
 
     @property
     def workspace(self) -> int:

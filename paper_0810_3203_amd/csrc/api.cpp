@@ -29,8 +29,10 @@ struct tft_plan {
     uint32_t f;
     Schedule sched;
     std::vector<uint32_t> nwaves;  // per pass
-    void *dev = nullptr;           // device copy of jobs | progs | steps | ops
+    void *dev = nullptr;           // device copy of the descriptor blob (plan-owned)
     int dev_id = -1;
+    std::vector<char> blob;        // jobs | progs | steps | ops, 256-byte aligned tables
+    size_t bj = 0, bp = 0, bs = 0, bo = 0;
     Job *d_jobs = nullptr;
     LeafProg *d_progs = nullptr;
     LeafStep *d_steps = nullptr;
@@ -119,27 +121,48 @@ int check_transform_args(const tft_ring *ring, uint32_t dir, uint32_t l, uint64_
     return TFT_OK;
 }
 
+// The plan's descriptors as one host blob: jobs | programs | steps | ops,
+// each table 256-byte aligned.  Built once per plan; copied to the device at
+// tft_plan_create (plan-owned memory) or, for the one-call transforms, into
+// the caller's workspace on every call.
+void plan_blob(tft_plan *p) {
+    if (!p->blob.empty()) return;
+    const Schedule &S = p->sched;
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    p->bj = al(S.jobs.size() * sizeof(Job));
+    p->bp = al(S.progs.size() * sizeof(LeafProg));
+    p->bs = al(S.steps.size() * sizeof(LeafStep));
+    p->bo = al(std::max<size_t>(1, S.ops.size()) * sizeof(LeafOp));
+    p->blob.assign(p->bj + p->bp + p->bs + p->bo, 0);
+    char *c = p->blob.data();
+    if (!S.jobs.empty()) memcpy(c, S.jobs.data(), S.jobs.size() * sizeof(Job));
+    if (!S.progs.empty()) memcpy(c + p->bj, S.progs.data(), S.progs.size() * sizeof(LeafProg));
+    if (!S.steps.empty()) memcpy(c + p->bj + p->bp, S.steps.data(), S.steps.size() * sizeof(LeafStep));
+    if (!S.ops.empty()) memcpy(c + p->bj + p->bp + p->bs, S.ops.data(), S.ops.size() * sizeof(LeafOp));
+}
+
+// Descriptor pointers of a blob placed at device address d.
+void plan_point(tft_plan *p, void *d) {
+    char *c = static_cast<char *>(d);
+    p->d_jobs = reinterpret_cast<Job *>(c);
+    p->d_progs = reinterpret_cast<LeafProg *>(c + p->bj);
+    p->d_steps = reinterpret_cast<LeafStep *>(c + p->bj + p->bp);
+    p->d_ops = reinterpret_cast<LeafOp *>(c + p->bj + p->bp + p->bs);
+}
+
 int plan_upload(tft_plan *p) {
     int dev = 0;
     hipError_t ge = hipGetDevice(&dev);
     if (ge != hipSuccess) return dev_fail(ge, "hipGetDevice");
-    if (p->dev && p->dev_id == dev) return TFT_OK;
-    const Schedule &S = p->sched;
-    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-    const size_t bj = al(S.jobs.size() * sizeof(Job)), bp = al(S.progs.size() * sizeof(LeafProg));
-    const size_t bs = al(S.steps.size() * sizeof(LeafStep)), bo = al(std::max<size_t>(1, S.ops.size()) * sizeof(LeafOp));
+    if (p->dev && p->dev_id == dev) {
+        plan_point(p, p->dev);
+        return TFT_OK;
+    }
+    plan_blob(p);
     void *buf = nullptr;
-    hipError_t me = hipMalloc(&buf, bj + bp + bs + bo);
+    hipError_t me = hipMalloc(&buf, p->blob.size());
     if (me != hipSuccess) return dev_fail(me, "hipMalloc(plan)");
-    char *c = static_cast<char *>(buf);
-    hipError_t e = hipSuccess;
-    if (!S.jobs.empty()) e = hipMemcpy(c, S.jobs.data(), S.jobs.size() * sizeof(Job), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !S.progs.empty())
-        e = hipMemcpy(c + bj, S.progs.data(), S.progs.size() * sizeof(LeafProg), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !S.steps.empty())
-        e = hipMemcpy(c + bj + bp, S.steps.data(), S.steps.size() * sizeof(LeafStep), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !S.ops.empty())
-        e = hipMemcpy(c + bj + bp + bs, S.ops.data(), S.ops.size() * sizeof(LeafOp), hipMemcpyHostToDevice);
+    hipError_t e = hipMemcpy(buf, p->blob.data(), p->blob.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(buf);
         return dev_fail(e, "hipMemcpy(plan)");
@@ -147,10 +170,7 @@ int plan_upload(tft_plan *p) {
     if (p->dev) (void)hipFree(p->dev);
     p->dev = buf;
     p->dev_id = dev;
-    p->d_jobs = reinterpret_cast<Job *>(c);
-    p->d_progs = reinterpret_cast<LeafProg *>(c + bj);
-    p->d_steps = reinterpret_cast<LeafStep *>(c + bj + bp);
-    p->d_ops = reinterpret_cast<LeafOp *>(c + bj + bp + bs);
+    plan_point(p, p->dev);
     return TFT_OK;
 }
 
@@ -226,12 +246,14 @@ struct LaunchTimer {
     }
 };
 
-int plan_run(tft_plan *p, void *x, hipStream_t st, LaunchTimer *lt = nullptr, bool transposed = false) {
-    std::lock_guard<std::mutex> lk(p->mu);
+bool plan_fits(const tft_plan *p) {
     for (const PassDesc &pd : p->sched.passes)
-        if ((uint64_t)pd.max_len * cell_lds_bytes(&p->ring) > lds_budget_bytes()) return TFT_E_UNSUPPORTED;
-    int rc = plan_upload(p);
-    if (rc) return rc;
+        if ((uint64_t)pd.max_len * cell_lds_bytes(&p->ring) > lds_budget_bytes()) return false;
+    return true;
+}
+
+// Launches the passes with the descriptor pointers already set (p->mu held).
+int plan_launch(tft_plan *p, void *x, hipStream_t st, LaunchTimer *lt, bool transposed) {
     const uint64_t cap = 1ull << p->l;
     const uint32_t ord_mask = ring_ord(&p->ring) - 1;
     for (size_t i = 0; i < p->sched.passes.size(); i++) {
@@ -250,6 +272,30 @@ int plan_run(tft_plan *p, void *x, hipStream_t st, LaunchTimer *lt = nullptr, bo
         if (lt && (e = lt->mark(st, false)) != hipSuccess) return dev_fail(e, "timer");
     }
     return TFT_OK;
+}
+
+// Runs a plan from its plan-owned device descriptors (uploaded on first use).
+int plan_run(tft_plan *p, void *x, hipStream_t st, LaunchTimer *lt = nullptr, bool transposed = false) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (!plan_fits(p)) return TFT_E_UNSUPPORTED;
+    int rc = plan_upload(p);
+    if (rc) return rc;
+    return plan_launch(p, x, st, lt, transposed);
+}
+
+// Runs a plan from descriptors copied into the caller's workspace on the
+// stream (no device memory of the library's own).
+int plan_run_ws(tft_plan *p, void *x, void *ws, uint64_t ws_bytes, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (!plan_fits(p)) return TFT_E_UNSUPPORTED;
+    plan_blob(p);
+    if (!ws || ws_bytes < p->blob.size() || (reinterpret_cast<uintptr_t>(ws) & 255u)) return TFT_E_WORKSPACE;
+    hipError_t e = hipMemcpyAsync(ws, p->blob.data(), p->blob.size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return dev_fail(e, "hipMemcpyAsync(descriptors)");
+    plan_point(p, ws);
+    const int rc = plan_launch(p, x, st, nullptr, false);
+    if (p->dev) plan_point(p, p->dev);
+    return rc;
 }
 
 // cache of plans used by the one-call entry points
@@ -313,7 +359,21 @@ int tft_plan_create(const tft_ring *ring, uint32_t direction, uint32_t l, uint64
     int st = check_transform_args(ring, direction, l, z, n, f);
     if (st) return st;
     if (split && split->top_l1 && split->top_l1 != TFT_SPLIT_DC && split->top_l1 >= l) return TFT_E_ARG;
-    *plan = plan_build(ring, direction, l, s, z, n, f, split);
+    tft_plan *p = plan_build(ring, direction, l, s, z, n, f, split);
+    // descriptors go to the current device now, so that executing the plan
+    // there allocates nothing.  Without a device (schedule inspection on a
+    // host) and for leaves beyond the LDS the plan stays host-only.
+    int ndev = 0;
+    const bool have_dev = hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0;
+    if (!have_dev) (void)hipGetLastError();
+    if (have_dev && plan_fits(p)) {
+        int rc = plan_upload(p);
+        if (rc) {
+            delete p;
+            return rc;
+        }
+    }
+    *plan = p;
     return TFT_OK;
 }
 
@@ -378,19 +438,34 @@ int tft_plan_export(const tft_plan *plan, uint64_t *buf, uint64_t cap_words, uin
     return TFT_OK;
 }
 
-int tft_forward(const tft_ring *ring, uint32_t l, uint64_t s, uint64_t z, uint64_t n, void *x, void *stream) {
+int tft_transform_workspace(const tft_ring *ring, uint32_t direction, uint32_t l, uint64_t s, uint64_t z, uint64_t n,
+                            uint32_t f, uint64_t *bytes) {
+    if (!bytes || direction > 1) return TFT_E_ARG;
+    int st = check_transform_args(ring, direction, l, z, n, f);
+    if (st) return st;
+    tft_plan *p = cached_plan(ring, direction, l, s, z, n, f, nullptr);
+    std::lock_guard<std::mutex> lk(p->mu);
+    plan_blob(p);
+    *bytes = p->blob.size();
+    return TFT_OK;
+}
+
+int tft_forward(const tft_ring *ring, uint32_t l, uint64_t s, uint64_t z, uint64_t n, void *x, void *ws,
+                uint64_t ws_bytes, void *stream) {
     int st = check_transform_args(ring, 0, l, z, n, 0);
     if (st) return st;
     if (!x) return TFT_E_ARG;
-    return plan_run(cached_plan(ring, 0, l, s, z, n, 0, nullptr), x, static_cast<hipStream_t>(stream));
+    return plan_run_ws(cached_plan(ring, 0, l, s, z, n, 0, nullptr), x, ws, ws_bytes,
+                       static_cast<hipStream_t>(stream));
 }
 
-int itft_inverse(const tft_ring *ring, uint32_t l, uint64_t s, uint64_t z, uint64_t n, uint32_t f, void *x,
-                 void *stream) {
+int itft_inverse(const tft_ring *ring, uint32_t l, uint64_t s, uint64_t z, uint64_t n, uint32_t f, void *x, void *ws,
+                 uint64_t ws_bytes, void *stream) {
     int st = check_transform_args(ring, 1, l, z, n, f);
     if (st) return st;
     if (!x) return TFT_E_ARG;
-    return plan_run(cached_plan(ring, 1, l, s, z, n, f, nullptr), x, static_cast<hipStream_t>(stream));
+    return plan_run_ws(cached_plan(ring, 1, l, s, z, n, f, nullptr), x, ws, ws_bytes,
+                       static_cast<hipStream_t>(stream));
 }
 
 int tft_debug_base_cases(const tft_ring *ring, uint32_t ncases, const void *cases, void *out, void *stream) {

@@ -100,8 +100,11 @@ uint32_t append_programs(Group &G, const Schedule &S) {
 struct tft_batch_plan {
     std::vector<Chunk> chunks;
     std::vector<int> status;
+    std::vector<tft_ss_params> params;  // what each request was planned with
     uint64_t ws_bytes = 0;
     bool uploaded = false;
+    int dev_id = -1;
+    hipStream_t capture = nullptr;  // stream that graph captures record on
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     void *graph_ws = nullptr;
@@ -172,15 +175,52 @@ hipError_t run_plan(tft_batch_plan *P, char *ws, hipStream_t st) {
     return hipSuccess;
 }
 
+// Uploads every group's descriptors and makes the capture stream on the
+// current device.
+int plan_prepare(tft_batch_plan *P) {
+    int dev = 0;
+    hipError_t ge = hipGetDevice(&dev);
+    if (ge != hipSuccess) return device_error(ge, "batch: hipGetDevice");
+    for (Chunk &C : P->chunks)
+        for (Group &G : C.groups) {
+            int rc = upload_group(G);
+            if (rc) return rc;
+        }
+    hipError_t ce = hipStreamCreateWithFlags(&P->capture, hipStreamNonBlocking);
+    if (ce != hipSuccess) {
+        P->capture = nullptr;
+        return device_error(ce, "batch: hipStreamCreateWithFlags");
+    }
+    P->uploaded = true;
+    P->dev_id = dev;
+    return TFT_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-int tft_batch_plan_create(const tft_zx_request *reqs, uint32_t count, uint64_t max_workspace,
-                          tft_batch_plan **plan) {
-    if (!plan || (!reqs && count)) return TFT_E_ARG;
+int tft_batch_plan_create(const tft_zx_request *reqs_in, uint32_t count, uint64_t max_workspace, int policy,
+                          tft_mlp *model, tft_batch_plan **plan) {
+    if (!plan || (!reqs_in && count)) return TFT_E_ARG;
+    if (policy != TFT_POLICY_GIVEN && policy != TFT_POLICY_RULE && policy != TFT_POLICY_MODEL) return TFT_E_ARG;
+    if (policy == TFT_POLICY_MODEL && !model) return TFT_E_ARG;
+    // the parameters every request is planned with
+    std::vector<tft_zx_request> rq(reqs_in, reqs_in + count);
+    if (policy == TFT_POLICY_RULE) {
+        for (tft_zx_request &r : rq) {
+            tft_ss_params d{};
+            if (tft_ss_default_params(r.len_g, r.g_limbs, r.len_h, r.h_limbs, &d) == TFT_OK) r.params = d;
+        }
+    } else if (policy == TFT_POLICY_MODEL && count) {
+        const int rc = tft_mlp_choose_ss(model, rq.data(), count, nullptr);
+        if (rc) return rc;
+    }
+    const tft_zx_request *reqs = rq.data();
     tft_batch_plan *P = new tft_batch_plan();
     P->status.assign(count, TFT_OK);
+    P->params.resize(count);
+    for (uint32_t i = 0; i < count; i++) P->params[i] = rq[i].params;
     std::vector<SSShape> shapes(count);
     for (uint32_t i = 0; i < count; i++) {
         const tft_zx_request &r = reqs[i];
@@ -310,7 +350,26 @@ int tft_batch_plan_create(const tft_zx_request *reqs, uint32_t count, uint64_t m
         P->ws_bytes = std::max(P->ws_bytes, C.bytes);
         P->chunks.push_back(std::move(C));
     }
+    // descriptors and the capture stream are made now, on the current device,
+    // so that executions allocate nothing; without a device the plan stays
+    // host-only (its workspace, status and launch counts can be read)
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) {
+        int rc = plan_prepare(P);
+        if (rc) {
+            tft_batch_plan_destroy(P);
+            return rc;
+        }
+    } else {
+        (void)hipGetLastError();
+    }
     *plan = P;
+    return TFT_OK;
+}
+
+int tft_batch_plan_params(const tft_batch_plan *plan, tft_ss_params *params) {
+    if (!plan || (!params && !plan->params.empty())) return TFT_E_ARG;
+    std::copy(plan->params.begin(), plan->params.end(), params);
     return TFT_OK;
 }
 
@@ -336,14 +395,14 @@ int tft_batch_plan_execute(tft_batch_plan *plan, void *ws, uint64_t ws_bytes, in
     if (!plan || (!ws && plan->ws_bytes)) return TFT_E_ARG;
     if (ws_bytes < plan->ws_bytes) return TFT_E_WORKSPACE;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    hipError_t de = hipGetDevice(&dev);
+    if (de != hipSuccess) return device_error(de, "batch: hipGetDevice");
     if (!plan->uploaded) {
-        for (Chunk &C : plan->chunks)
-            for (Group &G : C.groups) {
-                int rc = upload_group(G);
-                if (rc) return rc;
-            }
-        plan->uploaded = true;
+        int rc = plan_prepare(plan);  // created without a device present
+        if (rc) return rc;
     }
+    if (dev != plan->dev_id) return TFT_E_ARG;  // descriptors live on the creating device
     char *w = static_cast<char *>(ws);
     if (!use_graph) {
         hipError_t e = run_plan(plan, w, st);
@@ -359,9 +418,7 @@ int tft_batch_plan_execute(tft_batch_plan *plan, void *ws, uint64_t ws_bytes, in
             plan->exec = nullptr;
             plan->graph = nullptr;
         }
-        hipStream_t cs;
-        hipError_t ce = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-        if (ce != hipSuccess) return device_error(ce, "batch: hipStreamCreateWithFlags");
+        hipStream_t cs = plan->capture;
         hipError_t e = hipStreamSynchronize(st);
         if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
@@ -370,7 +427,6 @@ int tft_batch_plan_execute(tft_batch_plan *plan, void *ws, uint64_t ws_bytes, in
             if (le != hipSuccess) e = le;
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
-        (void)hipStreamDestroy(cs);
         if (e != hipSuccess) return device_error(e, "batch: graph capture");
         plan->graph_ws = ws;
         return TFT_OK;  // the eager run already produced this call's results
@@ -383,6 +439,7 @@ void tft_batch_plan_destroy(tft_batch_plan *plan) {
     if (!plan) return;
     if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->capture) (void)hipStreamDestroy(plan->capture);
     for (Chunk &C : plan->chunks)
         for (Group &G : C.groups)
             if (G.dev) (void)hipFree(G.dev);

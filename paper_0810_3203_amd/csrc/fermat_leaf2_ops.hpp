@@ -118,6 +118,7 @@ struct Big {
                 uint32_t z[C];
 #pragma unroll
                 for (int j = 0; j < C; ++j) z[j] = 0u;
+                wave_sync();  // after lane 0's last ripple store to these words
                 st(sm, e, z);
                 top = 1u;
             }

@@ -65,7 +65,8 @@ def test_ring_check():
 ])
 def test_tft_forward_rejects_bad_arguments(args, code):
     l, s, z, n = args
-    rc = T.lib().tft_forward(ctypes.byref(T.fermat_ring(512)), l, s, z, n, ctypes.c_void_p(1), None)
+    rc = T.lib().tft_forward(ctypes.byref(T.fermat_ring(512)), l, s, z, n, ctypes.c_void_p(1), ctypes.c_void_p(256),
+                             1 << 20, None)
     assert rc == code
 
 
@@ -77,7 +78,8 @@ def test_tft_forward_rejects_bad_arguments(args, code):
 ])
 def test_itft_rejects_bad_arguments(args, code):
     l, s, z, n, f = args
-    rc = T.lib().itft_inverse(ctypes.byref(T.fermat_ring(512)), l, s, z, n, f, ctypes.c_void_p(1), None)
+    rc = T.lib().itft_inverse(ctypes.byref(T.fermat_ring(512)), l, s, z, n, f, ctypes.c_void_p(1),
+                              ctypes.c_void_p(256), 1 << 20, None)
     assert rc == code
 
 
@@ -105,3 +107,51 @@ def test_plans_are_host_objects():
     p.close()
     with pytest.raises(T.TFTError):
         T.Plan(T.fermat_ring(512), 1, 10, 0, 10, 11)
+
+
+def test_transform_workspace_contract():
+    """tft_forward / itft_inverse take their descriptors in a caller workspace:
+    a NULL, short or misaligned one is refused before any device work."""
+    ring = T.fermat_ring(1024)
+    need = T.transform_workspace(ring, 0, 11, 3, 1500, 1700)
+    assert need > 0 and need % 256 == 0
+    assert T.transform_workspace(ring, 1, 11, 3, 1700, 1700, 0) > 0
+    L = T.lib()
+    x = ctypes.c_void_p(1)
+    for ws, nb in [(None, need), (ctypes.c_void_p(256), need - 1), (ctypes.c_void_p(257), need)]:
+        assert L.tft_forward(ctypes.byref(ring), 11, 3, 1500, 1700, x, ws, nb, None) == 4
+        assert L.itft_inverse(ctypes.byref(ring), 11, 3, 1700, 1700, 0, x, ws, nb, None) == 4
+    b = ctypes.c_uint64(0)
+    assert L.tft_transform_workspace(ctypes.byref(ring), 2, 11, 0, 1, 1, 0, ctypes.byref(b)) == 1
+    assert L.tft_transform_workspace(ctypes.byref(ring), 0, 11, 0, 0, 1, 0, ctypes.byref(b)) == 1
+
+
+def _dummy_requests(shapes):
+    reqs = []
+    for lg, gl, lh, hl in shapes:
+        bits = 32 * (gl + hl) + max(0, (min(lg, lh) - 1).bit_length())
+        reqs.append(T.ZXRequest(1, lg, gl, 1, lh, hl, 1, (bits + 31) // 32))
+    return T.requests_array(reqs)
+
+
+def test_batch_plan_policies_on_host():
+    """Policy RULE plans every request with the default rule whatever its params
+    say; GIVEN keeps them; an unknown policy or MODEL without a model is refused."""
+    shapes = [(500, 2, 500, 2), (3000, 63, 2000, 63), (40, 1, 7000, 5)]
+    arr = _dummy_requests(shapes)
+    cands = T.ss_candidates(*shapes[1])
+    arr[1].params = cands[-1]
+    given = T.BatchPlan(arr, policy=T.POLICY_GIVEN)
+    rule = T.BatchPlan(arr, policy=T.POLICY_RULE)
+    assert given.status() == [0, 0, 0] and rule.status() == [0, 0, 0]
+    for i, sh in enumerate(shapes):
+        d = T.ss_default_params(*sh)
+        r = rule.params()[i]
+        assert (r.k, r.N, r.l, r.split.top_l1, r.pad_rows) == (d.k, d.N, d.l, d.split.top_l1, d.pad_rows)
+    g = given.params()[1]
+    assert (g.k, g.N, g.l, g.pad_rows) == (cands[-1].k, cands[-1].N, cands[-1].l, cands[-1].pad_rows)
+    p = ctypes.c_void_p()
+    assert T.lib().tft_batch_plan_create(arr, 3, 0, 7, None, ctypes.byref(p)) == 1
+    assert T.lib().tft_batch_plan_create(arr, 3, 0, T.POLICY_MODEL, None, ctypes.byref(p)) == 1
+    given.close()
+    rule.close()
