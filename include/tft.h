@@ -204,6 +204,23 @@ int zx_mul_ss(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uint32_
               uint32_t h_limbs, uint32_t *out, uint32_t out_limbs, const tft_ss_params *params, void *ws,
               uint64_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * serving loops that forbid hipMalloc): zx_mul_ss with the same arguments
+ * minus the workspace, run from a static device array of
+ * TFT_STATIC_SCRATCH_BYTES bytes that the library holds on every device it
+ * runs on until the process ends.  The array takes the product's cell arrays
+ * (zx_mul_ss_workspace bytes, rounded up to 256) and the descriptors of its
+ * three transforms (a few KB); a request that needs more returns
+ * TFT_E_WORKSPACE (tft_last_error names both sizes) before any device work.
+ * Allocates no device memory (the first call with a new shape builds its plans
+ * on the host).  Every call on one device uses the same array: calls that
+ * overlap on a device (two streams, two threads) race and give wrong
+ * results; calls in one stream order are safe.  The output equals
+ * zx_mul_ss's bit for bit. */
+#define TFT_STATIC_SCRATCH_BYTES (32ull << 20)
+int zx_mul_ss_static(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uint32_t *h, uint64_t len_h,
+                     uint32_t h_limbs, uint32_t *out, uint32_t out_limbs, const tft_ss_params *params, void *stream);
+
 /* Phase times of one zx_mul_ss call, from HIP events recorded on its stream. */
 typedef struct {
     float pack_ms, tft_g_ms, tft_h_ms, pointwise_ms, itft_ms, unpack_ms, total_ms;

@@ -15,6 +15,7 @@ from ._binding import (  # noqa: F401
     POLICY_RULE,
     SPLIT_DC,
     SS_FEATURES,
+    STATIC_SCRATCH_BYTES,
     BatchPlan,
     Plan,
     SSParams,
@@ -41,6 +42,7 @@ from ._binding import (  # noqa: F401
     zmx_mul_nussbaumer,
     zmx_mul_nussbaumer_workspace,
     zx_mul_ss,
+    zx_mul_ss_static,
     zx_mul_ss_timed,
     zx_mul_ss_workspace,
     zx_request,
@@ -53,4 +55,5 @@ __all__ = [
     "zmx_mul_nussbaumer", "zmx_mul_nussbaumer_workspace", "zx_mul_ss", "zx_mul_ss_timed", "zx_mul_ss_workspace",
     "BatchPlan", "MLP", "SPLIT_DC", "SS_FEATURES", "ZXRequest", "requests_array", "ss_candidates", "ss_default_params",
     "ss_features", "ss_time", "zx_request", "POLICY_GIVEN", "POLICY_RULE", "POLICY_MODEL", "transform_workspace",
+    "STATIC_SCRATCH_BYTES", "zx_mul_ss_static",
 ]

@@ -64,6 +64,7 @@ class ZXRequest(ctypes.Structure):
 
 
 SS_FEATURES = 13
+STATIC_SCRATCH_BYTES = 32 << 20
 
 
 def fermat_ring(N: int) -> Ring:
@@ -111,6 +112,8 @@ def lib():
         L.zx_mul_ss_workspace.restype = I
         L.zx_mul_ss.argtypes = [P, U64, U32, P, U64, U32, P, U32, ctypes.POINTER(SSParams), P, U64, P]
         L.zx_mul_ss.restype = I
+        L.zx_mul_ss_static.argtypes = [P, U64, U32, P, U64, U32, P, U32, ctypes.POINTER(SSParams), P]
+        L.zx_mul_ss_static.restype = I
         L.zx_mul_ss_timed.argtypes = [P, U64, U32, P, U64, U32, P, U32, ctypes.POINTER(SSParams), P, U64, P,
                                       ctypes.POINTER(SSTiming)]
         L.zx_mul_ss_timed.restype = I
@@ -274,6 +277,15 @@ def zx_mul_ss(g, h, out, params=None, ws=None, stream=None):
     _check(lib().zx_mul_ss(_ptr(g), len_g, g_limbs, _ptr(h), len_h, h_limbs, _ptr(out), out_limbs,
                            ctypes.byref(params) if params else None, _ptr(ws), ws.numel() * ws.element_size(),
                            _stream(stream)), "zx_mul_ss")
+    return out
+
+
+def zx_mul_ss_static(g, h, out, params=None, stream=None):
+    """zx_mul_ss from the library's static device scratch (no workspace, no allocation)."""
+    len_g, g_limbs = g.shape
+    len_h, h_limbs = h.shape
+    _check(lib().zx_mul_ss_static(_ptr(g), len_g, g_limbs, _ptr(h), len_h, h_limbs, _ptr(out), out.shape[1],
+                                  ctypes.byref(params) if params else None, _stream(stream)), "zx_mul_ss_static")
     return out
 
 

@@ -285,7 +285,8 @@ int plan_run(tft_plan *p, void *x, hipStream_t st, LaunchTimer *lt = nullptr, bo
 
 // Runs a plan from descriptors copied into the caller's workspace on the
 // stream (no device memory of the library's own).
-int plan_run_ws(tft_plan *p, void *x, void *ws, uint64_t ws_bytes, hipStream_t st) {
+int plan_run_ws(tft_plan *p, void *x, void *ws, uint64_t ws_bytes, hipStream_t st, LaunchTimer *lt = nullptr,
+                bool transposed = false) {
     std::lock_guard<std::mutex> lk(p->mu);
     if (!plan_fits(p)) return TFT_E_UNSUPPORTED;
     plan_blob(p);
@@ -293,7 +294,7 @@ int plan_run_ws(tft_plan *p, void *x, void *ws, uint64_t ws_bytes, hipStream_t s
     hipError_t e = hipMemcpyAsync(ws, p->blob.data(), p->blob.size(), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return dev_fail(e, "hipMemcpyAsync(descriptors)");
     plan_point(p, ws);
-    const int rc = plan_launch(p, x, st, nullptr, false);
+    const int rc = plan_launch(p, x, st, lt, transposed);
     if (p->dev) plan_point(p, p->dev);
     return rc;
 }
@@ -510,18 +511,19 @@ int zx_mul_ss_workspace(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32
     return TFT_OK;
 }
 
-static int ss_run(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uint32_t *h, uint64_t len_h,
-                  uint32_t h_limbs, uint32_t *out, uint32_t out_limbs, const tft_ss_params *params, void *ws,
-                  uint64_t ws_bytes, hipStream_t hs, tft_ss_timing *tm) {
-    if (!g || !h || !out) return TFT_E_ARG;
+// The three transform plans of a product (TFT of g, TFT of h, ITFT).
+struct SSPlans {
     SSShape sh;
+    tft_plan *pg, *ph, *pi;
+};
+
+static int ss_plans(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h_limbs, uint32_t out_limbs,
+             const tft_ss_params *params, SSPlans *o) {
+    SSShape &sh = o->sh;
     int st = ss_shape(len_g, g_limbs, len_h, h_limbs, params, &sh);
     if (st) return st;
     if (32ull * out_limbs < sh.bits) return TFT_E_RANGE;
-    if (!ws || ws_bytes < sh.bytes) return TFT_E_WORKSPACE;
     tft_ring ring{TFT_RING_FERMAT, sh.N, 0, 0, 0};
-    uint32_t *A = static_cast<uint32_t *>(ws);
-    uint32_t *B = A + sh.L * (sh.W + 1);
     // One product on its own: unless the caller chose the leaf, cap it so that a
     // pass still has about two leaf jobs per compute unit (larger leaves mean
     // fewer passes, but a pass of fewer jobs than CUs leaves the GPU part idle);
@@ -529,10 +531,44 @@ static int ss_run(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uin
     // workgroup running every level alone.
     tft_split sp = params ? params->split : tft_split{0, 0};
     if (!sp.leaf_log2) sp.leaf_log2 = ss_leaf_log2(sh.N, sh.l);
-    const tft_split *split = &sp;
-    tft_plan *pg = cached_plan(&ring, 0, sh.l, sh.s, sh.zg, sh.nt, 0, split);
-    tft_plan *ph = cached_plan(&ring, 0, sh.l, sh.s, sh.zh, sh.nt, 0, split);
-    tft_plan *pi = cached_plan(&ring, 1, sh.l, (2ull * sh.s) % (2ull * sh.N), sh.nt, sh.nt, 0, split);
+    o->pg = cached_plan(&ring, 0, sh.l, sh.s, sh.zg, sh.nt, 0, &sp);
+    o->ph = cached_plan(&ring, 0, sh.l, sh.s, sh.zh, sh.nt, 0, &sp);
+    o->pi = cached_plan(&ring, 1, sh.l, (2ull * sh.s) % (2ull * sh.N), sh.nt, sh.nt, 0, &sp);
+    return TFT_OK;
+}
+
+static uint64_t blob_bytes(tft_plan *p) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    plan_blob(p);
+    return p->blob.size();
+}
+
+// desc == nullptr: the plans run from their own device descriptors (uploaded
+// on first use).  Otherwise the three plans' descriptors are copied into
+// desc (desc_bytes >= the sum of their blobs) on the stream.
+static int ss_run(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uint32_t *h, uint64_t len_h, uint32_t h_limbs,
+           uint32_t *out, uint32_t out_limbs, const tft_ss_params *params, void *ws, uint64_t ws_bytes,
+           hipStream_t hs, tft_ss_timing *tm, char *desc = nullptr, uint64_t desc_bytes = 0) {
+    if (!g || !h || !out) return TFT_E_ARG;
+    SSPlans P;
+    int st = ss_plans(len_g, g_limbs, len_h, h_limbs, out_limbs, params, &P);
+    if (st) return st;
+    const SSShape &sh = P.sh;
+    if (!ws || ws_bytes < sh.bytes) return TFT_E_WORKSPACE;
+    uint32_t *A = static_cast<uint32_t *>(ws);
+    uint32_t *B = A + sh.L * (sh.W + 1);
+    tft_plan *pg = P.pg, *ph = P.ph, *pi = P.pi;
+    char *dg_at = nullptr, *dh_at = nullptr, *di_at = nullptr;
+    uint64_t bg = 0, bh = 0, bi = 0;
+    if (desc) {
+        bg = blob_bytes(pg);
+        bh = blob_bytes(ph);
+        bi = blob_bytes(pi);
+        if (desc_bytes < bg + bh + bi) return TFT_E_WORKSPACE;
+        dg_at = desc;
+        dh_at = desc + bg;
+        di_at = desc + bg + bh;
+    }
     hipEvent_t ev[7] = {};
     LaunchTimer lt;
     LaunchTimer *ltp = tm ? &lt : nullptr;
@@ -550,16 +586,19 @@ static int ss_run(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uin
     if (e == hipSuccess) e = launch_fermat_pack(sh.W, nullptr, 1, dh, sh.zh, B, sh.L, true, hs);
     if (e == hipSuccess) e = mark(1);
     if (e != hipSuccess) st = dev_fail(e, "pack");
-    if (!st) st = plan_run(pg, A, hs, ltp, true);
+    auto run = [&](tft_plan *p, uint32_t *x, char *d, uint64_t b) {
+        return d ? plan_run_ws(p, x, d, b, hs, ltp, true) : plan_run(p, x, hs, ltp, true);
+    };
+    if (!st) st = run(pg, A, dg_at, bg);
     if (!st && (e = mark(2)) != hipSuccess) st = dev_fail(e, "event");
-    if (!st) st = plan_run(ph, B, hs, ltp, true);
+    if (!st) st = run(ph, B, dh_at, bh);
     if (!st && (e = mark(3)) != hipSuccess) st = dev_fail(e, "event");
     if (!st) {
         e = launch_fermat_pointwise(sh.W, sh.nt, A, B, A, sh.L, (uint32_t)((2 * sh.N - sh.l) % (2 * sh.N)), true, hs);
         if (e == hipSuccess) e = mark(4);
         if (e != hipSuccess) st = dev_fail(e, "pointwise");
     }
-    if (!st) st = plan_run(pi, A, hs, ltp, true);
+    if (!st) st = run(pi, A, di_at, bi);
     if (!st && (e = mark(5)) != hipSuccess) st = dev_fail(e, "event");
     if (!st) {
         const UnpackDesc du{out, len_g + len_h - 1, 0, sh.n, out_limbs, sh.k, sh.ws, 0};
@@ -592,6 +631,44 @@ static int ss_run(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uin
     }
     return st;
 }
+
+}  // extern "C"
+
+namespace tft {
+
+// Bytes of one scratch area holding a product's cell arrays followed by its
+// three plans' descriptors; 0 with *status set when the request is invalid.
+int ss_scratch_bytes(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h_limbs, uint32_t out_limbs,
+                     const tft_ss_params *params, uint64_t *bytes) {
+    SSPlans P;
+    int st = ss_plans(len_g, g_limbs, len_h, h_limbs, out_limbs, params, &P);
+    if (st) return st;
+    *bytes = ((P.sh.bytes + 255) & ~255ull) + blob_bytes(P.pg) + blob_bytes(P.ph) + blob_bytes(P.pi);
+    return TFT_OK;
+}
+
+int ss_scratch_run(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uint32_t *h, uint64_t len_h,
+                   uint32_t h_limbs, uint32_t *out, uint32_t out_limbs, const tft_ss_params *params, void *scratch,
+                   uint64_t scratch_bytes, hipStream_t hs) {
+    SSShape sh;
+    int st = ss_shape(len_g, g_limbs, len_h, h_limbs, params, &sh);
+    if (st) return st;
+    const uint64_t cells = (sh.bytes + 255) & ~255ull;
+    if (cells > scratch_bytes) return TFT_E_WORKSPACE;
+    char *c = static_cast<char *>(scratch);
+    return ss_run(g, len_g, g_limbs, h, len_h, h_limbs, out, out_limbs, params, c, sh.bytes, hs, nullptr, c + cells,
+                  scratch_bytes - cells);
+}
+
+int set_error(int code, const char *msg) {
+    snprintf(g_last_error, sizeof g_last_error, "%s", msg);
+    if (getenv("TFT_DEBUG")) fprintf(stderr, "[tft] %s\n", g_last_error);
+    return code;
+}
+
+}  // namespace tft
+
+extern "C" {
 
 int zx_mul_ss(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uint32_t *h, uint64_t len_h,
               uint32_t h_limbs, uint32_t *out, uint32_t out_limbs, const tft_ss_params *params, void *ws,

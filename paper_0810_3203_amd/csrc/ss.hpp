@@ -4,6 +4,7 @@
 // limbs, wide enough for any output coefficient); a product cell then holds
 // 2k-1 slots, so N >= 32 (2k-1) ws, and L = 2^l must divide 2N.
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "../../include/tft.h"
@@ -77,5 +78,17 @@ inline int ss_shape(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h
     o->bits = bits;
     return TFT_OK;
 }
+
+// A product run from one device scratch area: its cell arrays first, then the
+// descriptors of its three transform plans (copied in on the stream).
+// ss_scratch_bytes: the area a request needs (host work: builds the plans).
+// ss_scratch_run: TFT_E_WORKSPACE if the request needs more than scratch_bytes.
+int ss_scratch_bytes(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h_limbs, uint32_t out_limbs,
+                     const tft_ss_params *params, uint64_t *bytes);
+int ss_scratch_run(const uint32_t *g, uint64_t len_g, uint32_t g_limbs, const uint32_t *h, uint64_t len_h,
+                   uint32_t h_limbs, uint32_t *out, uint32_t out_limbs, const tft_ss_params *params, void *scratch,
+                   uint64_t scratch_bytes, hipStream_t hs);
+// Sets the message tft_last_error returns; returns code.
+int set_error(int code, const char *msg);
 
 }  // namespace tft

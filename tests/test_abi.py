@@ -155,3 +155,19 @@ def test_batch_plan_policies_on_host():
     assert T.lib().tft_batch_plan_create(arr, 3, 0, T.POLICY_MODEL, None, ctypes.byref(p)) == 1
     given.close()
     rule.close()
+
+
+def test_static_scratch_product_rejects_oversized_requests():
+    """zx_mul_ss_static refuses a request whose cell arrays exceed the static
+    scratch before touching the device, and says how much it needed."""
+    L = T.lib()
+    one = ctypes.c_void_p(1)
+    # 10000 x 10000 coefficients of 10 limbs: about 128 MiB of cell arrays
+    rc = L.zx_mul_ss_static(one, 10000, 10, one, 10000, 10, one, 24, None, None)
+    assert rc == 4
+    msg = T.lib().tft_last_error().decode()
+    assert "limit is %d" % T.STATIC_SCRATCH_BYTES in msg
+    assert T.zx_mul_ss_workspace(10000, 10, 10000, 10) > T.STATIC_SCRATCH_BYTES
+    # the usual argument errors come first
+    assert L.zx_mul_ss_static(one, 10, 2, one, 10, 2, one, 4, None, None) == 3
+    assert L.zx_mul_ss_static(None, 10, 2, one, 10, 2, one, 6, None, None) == 1
