@@ -15,6 +15,7 @@ Inputs are resident in HBM before the timed region.  One JSON line is printed.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
     python bench.py --split-sweep     # cache-friendly vs divide-and-conquer transforms
+    python bench.py --alu-probe       # register-only issue rates behind the pointwise ceiling
 """
 
 import argparse
@@ -29,8 +30,20 @@ if ROOT not in sys.path:
 
 METRIC = "TFT+ITFT GB/s & % HBM peak; batched Z[x] muls/s vs one-at-a-time (bit-exact)"
 HBM_PEAK_GBS = 8000.0
-# 256 CUs x 16 lanes per clock (v_mad_u64_u32 issues at a quarter of the 64-lane rate) x 2.4 GHz
-MAD_PEAK_T = 256 * 16 * 2.4e9 / 1e12
+# MI355X: 256 compute units of 4 SIMDs at 2.4 GHz; a SIMD issues one wave64
+# VALU instruction per `cycles` clocks (4 for a full-rate operation)
+CUS, SIMDS, CLOCK_HZ, WAVE = 256, 4, 2.4e9, 64
+CPU_THREAD_CAP = 16  # worker threads the GPU host's CPU share allows
+
+
+def lane_ops_peak(cycles_per_wave_instr):
+    """Lane operations per second of one instruction issued back to back on every SIMD."""
+    return CUS * SIMDS * CLOCK_HZ * WAVE / cycles_per_wave_instr
+
+
+def cycles_per_wave_instr(lane_ops_per_s):
+    """Clocks per wave64 instruction implied by a measured issue rate at 2.4 GHz."""
+    return CUS * SIMDS * CLOCK_HZ * WAVE / lane_ops_per_s
 
 
 def _split(l):
@@ -66,11 +79,22 @@ def alg_cells_itft(l, z, n, f):
     return cells
 
 
-def cpu_baseline(g_limbs_arr, N, l, z, n, alg_bytes, budget_s=12.0):
-    """The oracle (eq. (1) evaluated directly, plain C) on a bounded sample, extrapolated."""
+def host_threads():
+    """(nproc, threads used): the CPUs this process may run on, capped at the
+    GPU host's share."""
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 1
+    return nproc, max(1, min(CPU_THREAD_CAP, nproc))
+
+
+def cpu_baseline(g_limbs_arr, N, l, z, n, alg_bytes, budget_s=12.0, one_thread_s=3.0):
+    """The oracle (eq. (1) evaluated directly, plain C) on a bounded sample, extrapolated;
+    on all threads the host allows, and on one thread."""
     import numpy as np
     from oracle import coracle
-    threads = min(16, os.cpu_count() or 1)
+    nproc, threads = host_threads()
     L = 1 << l
     W = N // 32
     a = np.zeros((z, W), dtype=np.uint32)
@@ -89,11 +113,79 @@ def cpu_baseline(g_limbs_arr, N, l, z, n, alg_bytes, budget_s=12.0):
     t_k = time.perf_counter() - t0
     per_output = t_k / k  # wall seconds per TFT output (z terms) with `threads` threads
     # the direct transforms: 2 TFTs of n outputs with z terms, one inverse of n outputs with n terms
-    total_s = per_output * (2 * n + n * (n / z))
-    return {"value": alg_bytes / total_s / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
-            "sample": "eq. (1) evaluated directly for %d output indices of TFT(g) (%d terms each) on %d threads, "
-                      "%.1f s; extrapolated by term count to TFT(g)+TFT(h)+ITFT (%.0f s)" % (k, z, threads, t_k,
-                                                                                          total_s)}
+    outputs = 2 * n + n * (n / z)
+    total_s = per_output * outputs
+    # one thread, on a smaller sample
+    k1 = max(1, min(k, int(one_thread_s / max(t_one, 1e-6))))
+    t0 = time.perf_counter()
+    coracle.fermat_dft_sampled(N, L, 0, a, tops, js[:k1], nthreads=1)
+    t_1 = time.perf_counter() - t0
+    total_1 = t_1 / k1 * outputs
+    return {"value": alg_bytes / total_s / 1e9, "unit": "GB/s", "cores": threads, "nproc": nproc,
+            "kind": "oracle", "one_thread_value": alg_bytes / total_1 / 1e9,
+            "sample": "eq. (1) evaluated directly for %d output indices of TFT(g) (%d terms each) on %d threads "
+                      "(nproc %d, capped at %d), %.1f s, and for %d of them on 1 thread, %.1f s; extrapolated by "
+                      "term count to TFT(g)+TFT(h)+ITFT (%.0f s on %d threads, %.0f s on 1)"
+                      % (k, z, threads, nproc, CPU_THREAD_CAP, t_k, k1, t_1, total_s, threads, total_1)}
+
+
+def alu_probe(T, blocks=None, iters=(16384, 8192, 4096)):
+    """Register-only issue rates (tft_alu_rate) of v_add_u32, v_mad_u64_u32 and the
+    two-instruction limb multiply-accumulate, and the clocks per wave instruction
+    they imply at 2.4 GHz.  The multiply-accumulate rate is the ceiling of the
+    pointwise kernel's inner loop."""
+    blocks = blocks or CUS * 8
+    out = {"blocks": blocks, "threads_per_block": 256}
+    for kind, name, it in ((0, "add_u32", iters[0]), (1, "mad_u64_u32", iters[1]), (2, "mac_pair", iters[2])):
+        best, hz_best = None, 0.0
+        for _ in range(3):
+            ms, ops, hz = T.alu_rate(kind, blocks, it)
+            rate = ops / (ms * 1e-3)
+            if best is None or rate > best:
+                best, hz_best = rate, hz
+        out[name + "_T_per_s"] = round(best / 1e12, 3)
+        out[name + "_cycles_per_wave_instr"] = round(cycles_per_wave_instr(best), 2)
+        out[name + "_clock_GHz"] = round(hz_best / 1e9, 3)
+        if hz_best > 0:  # clocks per instruction at the clock the probe measured
+            out[name + "_cycles_at_measured_clock"] = round(cycles_per_wave_instr(best) * hz_best / CLOCK_HZ, 2)
+    return out
+
+
+def nega_case4_transforms(T, torch, reps=5):
+    """The transforms of the (Z/mZ)[x] product, 500000 x 500000 with K = 1024: two
+    TFT(2^11, 977 -> 1953) and one ITFT(1953) over (Z/mZ)[y]/(y^1024+1), timed
+    one by one with HIP events (median of reps), as GB/s of algorithmic bytes
+    (the cells Alg. 1 / Alg. 2's top-level passes read and write, 8192 bytes each)."""
+    from synth import workloads as wl
+    m, _, _ = wl.zmx_operands()
+    K, l, z, n = 1024, 11, 977, 1953
+    ring = T.nega_ring(K, m)
+    L = 1 << l
+    x = torch.randint(0, 1 << 62, (L * K,), dtype=torch.int64, device="cuda") % m
+    wsf = torch.empty(T.transform_workspace(ring, 0, l, 0, z, n), dtype=torch.uint8, device="cuda")
+    wsi = torch.empty(T.transform_workspace(ring, 1, l, 0, n, n, 0), dtype=torch.uint8, device="cuda")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[len(ts) // 2]
+
+    tft_ms = timed(lambda: T.tft_forward(ring, l, 0, z, n, x, wsf))
+    itft_ms = timed(lambda: T.itft_inverse(ring, l, 0, n, n, 0, x, wsi))
+    cells = 2 * alg_cells_tft(l, z, n) + alg_cells_itft(l, n, n, 0)
+    total = 2 * tft_ms + itft_ms
+    gbs = cells * 8 * K / (total * 1e-3) / 1e9
+    return {"workload": "2 x TFT(2^11, z=977, n=1953) + ITFT(1953) over (Z/mZ)[y]/(y^1024+1)",
+            "tft_ms": round(tft_ms, 4), "itft_ms": round(itft_ms, 4), "alg_cells": cells,
+            "alg_bytes": cells * 8 * K, "gb_per_s": round(gbs, 2), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def _source_hash():
@@ -465,6 +557,10 @@ def main():
     ap.add_argument("--split-sweep", action="store_true",
                     help="instead of the benchmark: cache-friendly vs divide-and-conquer transforms over a sweep "
                          "of Z[x] products with 8000-bit coefficients (one JSON line)")
+    ap.add_argument("--large-only", action="store_true",
+                    help="only the large product (for profiler runs): no probe, other products or batch")
+    ap.add_argument("--alu-probe", action="store_true",
+                    help="instead of the benchmark: only the register-only issue-rate probe (one JSON line)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run three plain 1 GiB device copies (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -482,6 +578,9 @@ def main():
     torch.cuda.set_device(0)
     if args.split_sweep:
         print(json.dumps(split_sweep(T, torch)), flush=True)
+        return
+    if args.alu_probe:
+        print(json.dumps(alu_probe(T)), flush=True)
         return
     spec = wl.ZX_CASES[3]
     g, h = wl.zx_operands(3)
@@ -550,20 +649,24 @@ def main():
             "traffic": profiled_traffic(),
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "alg_bytes_per_launch": int(alg_bytes / max(1, launches)),
-            "kernel": "fermat_leaf_kernel<64,32> (%d launches per step)" % launches,
+            "kernel": "fermat_leaf2_kernel<32,true> (%d launches per step)" % launches,
             "avg_launch_ms": round(leaf_ms / max(1, launches), 4),
         },
-        # the pointwise stage is bound by the 32 x 32 -> 64-bit multiply-add
-        # (v_mad_u64_u32, quarter rate: 16 lanes per CU per clock)
-        "pointwise_roofline": {
-            "bound": "alu",
-            "achieved": round(n * (N // 32) ** 2 / (avg("pointwise_ms") * 1e-3) / 1e12, 3),
-            "peak": round(MAD_PEAK_T, 3),
-            "unit": "T limb multiply-adds/s",
-            "frac": round(n * (N // 32) ** 2 / (avg("pointwise_ms") * 1e-3) / 1e12 / MAD_PEAK_T, 4),
-            "kernel": "fermat_pointwise_kernel<64,32>: %d products of %d x %d limbs (schoolbook)" % (n, N // 32,
-                                                                                                  N // 32),
-        },
+    }
+    # the pointwise stage is bound by its limb multiply-accumulate (v_mad_u64_u32
+    # + v_addc_co_u32); its ceiling is that pair's register-only issue rate
+    probe = {} if args.large_only else _leg(lambda: alu_probe(T))
+    line["alu_probe"] = probe
+    mac_peak = probe.get("mac_pair_T_per_s")
+    pw_achieved = n * (N // 32) ** 2 / (avg("pointwise_ms") * 1e-3) / 1e12
+    line["pointwise_roofline"] = {
+        "bound": "alu",
+        "achieved": round(pw_achieved, 3),
+        "peak": mac_peak,
+        "unit": "T limb multiply-accumulates/s",
+        "frac": round(pw_achieved / mac_peak, 4) if mac_peak else None,
+        "peak_source": "alu_probe.mac_pair_T_per_s (register-only loop of the same two instructions)",
+        "kernel": "fermat_pointwise_kernel<64,32>: %d products of %d x %d limbs (schoolbook)" % (n, N // 32, N // 32),
     }
     if not args.no_padded:
         line["product_variants"] = _leg(lambda: padded_leg(T, torch, dg, dh, out, l, n, N, reps=3))
@@ -571,11 +674,14 @@ def main():
     torch.cuda.empty_cache()
     # a failing secondary leg is reported in the line (with its traceback on
     # stderr) instead of taking the measured headline with it
-    _progress("other products")
-    line["other_products"] = _leg(lambda: other_products(T, torch))
-    if not args.no_batch:
+    if not args.large_only:
+        _progress("other products")
+        line["other_products"] = _leg(lambda: other_products(T, torch))
+        _progress("(Z/mZ)[x] product transforms")
+        line["nega_case4_transforms"] = _leg(lambda: nega_case4_transforms(T, torch))
+    if not args.no_batch and not args.large_only:
         line["batch"] = _leg(lambda: batch_leg(T, torch))
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.large_only:
         _progress("cpu baseline (oracle sample)")
         line["cpu_baseline"] = cpu_baseline(g, N, l, len_g, n, alg_bytes)
     print(json.dumps(line), flush=True)

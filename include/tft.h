@@ -150,6 +150,20 @@ int itft_inverse(const tft_ring *ring, uint32_t l, uint64_t s, uint64_t z, uint6
  * the records after the base case.  TFT_E_UNSUPPORTED for other rings. */
 int tft_debug_base_cases(const tft_ring *ring, uint32_t ncases, const void *cases, void *out, void *stream);
 
+/* Measurement aid (not part of the paper): issue rate of the integer
+ * instructions the pointwise products are made of, from registers only.
+ * Launches `blocks` workgroups of 256 threads; each thread runs `iters`
+ * iterations over eight independent accumulators of
+ *   kind 0: v_add_u32,  kind 1: v_mad_u64_u32,
+ *   kind 2: v_mad_u64_u32 + v_addc_co_u32 (one limb multiply-accumulate),
+ * after one short untimed launch.  *ms = the timed launch's duration (HIP
+ * events on `stream`; waits for it), *lane_ops = blocks*256*iters*8
+ * operations of the kind, *clock_hz = the shader clock over workgroup 0's
+ * first wave (s_memtime cycles per 100 MHz s_memrealtime tick, times 1e8).
+ * TFT_E_ARG for kind > 2, zero sizes or NULL outputs. */
+int tft_alu_rate(uint32_t kind, uint32_t blocks, uint32_t iters, float *ms, uint64_t *lane_ops, double *clock_hz,
+                 void *stream);
+
 /* Pointwise products (Sect. 2: u_hat_i = g_hat_i h_hat_i, 0 <= i < n):
  *   c_i = a_i * b_i * 2^(-scale_log2) in R for 0 <= i < n.
  * a, b, c are cell arrays of capacity `cap` (n <= cap); c may alias a or b.

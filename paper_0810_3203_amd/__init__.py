@@ -21,6 +21,7 @@ from ._binding import (  # noqa: F401
     SSParams,
     Split,
     TFTError,
+    alu_rate,
     array_bytes,
     debug_base_cases,
     elem_bytes,
@@ -55,5 +56,5 @@ __all__ = [
     "zmx_mul_nussbaumer", "zmx_mul_nussbaumer_workspace", "zx_mul_ss", "zx_mul_ss_timed", "zx_mul_ss_workspace",
     "BatchPlan", "MLP", "SPLIT_DC", "SS_FEATURES", "ZXRequest", "requests_array", "ss_candidates", "ss_default_params",
     "ss_features", "ss_time", "zx_request", "POLICY_GIVEN", "POLICY_RULE", "POLICY_MODEL", "transform_workspace",
-    "STATIC_SCRATCH_BYTES", "zx_mul_ss_static",
+    "STATIC_SCRATCH_BYTES", "zx_mul_ss_static", "alu_rate",
 ]

@@ -104,6 +104,9 @@ def lib():
         L.tft_forward.restype = I
         L.itft_inverse.argtypes = [RP, U32, U64, U64, U64, U32, P, P, U64, P]
         L.itft_inverse.restype = I
+        L.tft_alu_rate.argtypes = [U32, U32, U32, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(U64),
+                                   ctypes.POINTER(ctypes.c_double), P]
+        L.tft_alu_rate.restype = I
         L.tft_debug_base_cases.argtypes = [RP, U32, P, P, P]
         L.tft_debug_base_cases.restype = I
         L.pointwise_mul.argtypes = [RP, U64, P, P, P, U64, U32, P]
@@ -243,6 +246,16 @@ def itft_inverse(ring, l, s, z, n, f, x, ws=None, stream=None):
     ws = _transform_ws(ring, 1, l, s, z, n, f, x, ws)
     _check(lib().itft_inverse(ctypes.byref(ring), l, s, z, n, f, _ptr(x), _ptr(ws),
                               ws.numel() * ws.element_size(), _stream(stream)), "itft_inverse")
+
+
+def alu_rate(kind, blocks, iters, stream=None):
+    """(ms, lane_ops, shader clock Hz) of the register-only issue-rate probe (tft_alu_rate)."""
+    ms = ctypes.c_float(0)
+    ops = ctypes.c_uint64(0)
+    hz = ctypes.c_double(0)
+    _check(lib().tft_alu_rate(kind, blocks, iters, ctypes.byref(ms), ctypes.byref(ops), ctypes.byref(hz),
+                              _stream(stream)), "tft_alu_rate")
+    return ms.value, ops.value, hz.value
 
 
 def debug_base_cases(ring, ncases, cases, out, stream=None):

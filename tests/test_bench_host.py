@@ -38,8 +38,16 @@ def test_full_transform_reads_and_writes_every_cell_twice():
         assert bench.alg_cells_itft(l, L, L, 0) == 4 * L
 
 
-def test_mad_peak():
-    assert abs(bench.MAD_PEAK_T - 9.8304) < 1e-9
+def test_issue_rate_and_cycles_are_inverse():
+    # a full-rate wave64 instruction (4 clocks) on 256 CUs x 4 SIMDs at 2.4 GHz
+    assert abs(bench.lane_ops_peak(4) - 256 * 4 * 2.4e9 * 16) < 1
+    for c in (4, 8, 16, 5.5):
+        assert abs(bench.cycles_per_wave_instr(bench.lane_ops_peak(c)) - c) < 1e-9
+
+
+def test_host_threads_capped():
+    nproc, used = bench.host_threads()
+    assert nproc >= 1 and 1 <= used <= min(nproc, bench.CPU_THREAD_CAP)
 
 
 def test_more_than_one_gpu_refused():

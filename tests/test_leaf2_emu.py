@@ -54,3 +54,51 @@ def test_base_cases_emulated(emu_exe, C, cases, seed):
         if y0 != e0 or (e1 is not None and y1 != e1) or not canon:
             bad.append((code, s, hex(x0)[:20], hex(x1)[:20]))
     assert not bad, "%d of %d base cases wrong, first: %s" % (len(bad), cases, bad[:5])
+
+
+def _emulate_plan(emu_exe, N, direction, l, s, z, n, f, leaf, cells):
+    """Runs an exported plan's jobs, pass after pass, on the emulated wave."""
+    import paper_0810_3203_amd as T
+    W = N // 32
+    L = 1 << l
+    e = T.Plan(T.fermat_ring(N), direction, l, s, z, n, f, 0, leaf).export()
+    ops = [(code | (i0 << 4) | (i1 << 18), (b & 0xFFFFFF) | (alog << 24)) for code, i0, i1, alog, b in e["ops"]]
+    jobs = []
+    for jb, jc, _ in e["passes"]:
+        jobs.extend(e["jobs"][jb:jb + jc])
+    lines = ["%d %d %d %d %d %d" % (L, e["ord"], len(e["progs"]), len(e["steps"]), len(ops), len(jobs))]
+    lines += ["%d %d %d" % p for p in e["progs"]]
+    lines += ["%d %d" % t for t in e["steps"]]
+    lines += ["%d %d" % o for o in ops]
+    lines += ["%d %d %d %d %d %d" % j for j in jobs]
+    for v in cells:
+        lines.append("%0*x %d" % (W * 8, v & ((1 << N) - 1), v >> N))
+    r = subprocess.run([emu_exe, "plan", str(W // 64)], input="\n".join(lines) + "\n", capture_output=True,
+                       text=True, timeout=600)
+    assert r.returncode == 0, r.stderr
+    out = []
+    for ln in r.stdout.strip().splitlines():
+        h, t = ln.split()
+        out.append(int(h, 16) + (int(t) << N))
+    return out
+
+
+@pytest.mark.parametrize("kind,s", [("sparse", 7), ("random", 1000)])
+def test_leaf_programs_emulated(emu_exe, kind, s):
+    """Whole transforms (two passes of 8-cell leaves) on the emulated wave: TFT
+    (Alg. 1) against eq. (1), and the ITFT (Alg. 2) of eq. (1)'s values against
+    L times the input.  Sparse inputs (half-width values) keep long zero runs, so
+    carries cross many lanes."""
+    import random
+    from oracle import tft_oracle as O
+    N, l, z, n = 8192, 6, 32, 63
+    ring = O.FermatRing(N)
+    L = 1 << l
+    rng = random.Random(s)
+    a = [rng.getrandbits(N // 2) if kind == "sparse" else rng.randrange(ring.p) for _ in range(z)]
+    a[0] = ring.p - 1
+    got = _emulate_plan(emu_exe, N, 0, l, s, z, n, 0, 3, a + [0] * (L - z))
+    assert got[:n] == O.tft(ring, L, s, z, n, a)
+    inputs, expect = O.itft_case(ring, L, s, n, n, 0, a + [0] * (n - z))
+    got = _emulate_plan(emu_exe, N, 1, l, s, n, n, 0, 3, list(inputs) + [0] * (L - n))
+    assert got[:n] == expect
