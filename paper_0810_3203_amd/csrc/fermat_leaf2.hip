@@ -20,26 +20,50 @@ uint32_t device_cus() {
     return (uint32_t)cache[dev];
 }
 
+// Jobs packed per workgroup for a pass of leaves of `slot` cells: as many as
+// the cells the kernel can hold (LDS, and 16 quads per thread), but never so
+// many that fewer packs than compute units remain.  Leaves of 8 cells and more
+// give at least half of the 8 waves a base case per step and are not packed
+// (measured: packing pairs of 8-cell leaves is slower than running them alone).
+uint32_t leaf2_pack(uint32_t W, uint32_t njobs, uint32_t slot) {
+    if (slot >= 8u) return 1u;
+    const uint32_t cap_quads = (uint32_t)lf2::kQuadsPerThread * lf2::kThreads / (W / 4u);
+    uint32_t cap_lds = 0;
+    while (lf2::lds_dwords(W, cap_lds + 1u) * 4u <= kLds) cap_lds++;
+    uint32_t cap = cap_quads < cap_lds ? cap_quads : cap_lds;
+    cap = cap < W ? cap : W;  // top words of the cells fit the guard block
+    uint32_t pack = cap / slot;
+    const uint32_t fill = njobs / device_cus();
+    if (pack > fill) pack = fill;
+    return pack < 1u ? 1u : pack;
+}
+
 template <int C, bool TR>
-hipError_t leaf2_launch(uint32_t njobs, uint32_t lds_cells, const Job *jobs, uint32_t job_offset,
-                        const LeafProg *progs, const LeafStep *steps, const LeafOp *ops, uint32_t *x, uint64_t cap,
-                        uint32_t ord_mask, hipStream_t st) {
+hipError_t leaf2_launch(uint32_t njobs, uint32_t slot, const Job *jobs, uint32_t job_offset, const LeafProg *progs,
+                        const LeafStep *steps, const LeafOp *ops, uint32_t *x, uint64_t cap, uint32_t ord_mask,
+                        hipStream_t st) {
     constexpr uint32_t W = 64u * C;
-    if (lds_cells == 0u || lds_cells * (W / 4u) > (uint32_t)lf2::kQuadsPerThread * lf2::kThreads || lds_cells > W)
+    uint32_t slot_log2 = 0;
+    while ((1u << slot_log2) < slot) slot_log2++;
+    if (slot == 0u || (1u << slot_log2) != slot) return hipErrorInvalidValue;
+    const uint32_t pack = leaf2_pack(W, njobs, slot);
+    const uint32_t lds_cells = pack * slot;
+    if (lds_cells * (W / 4u) > (uint32_t)lf2::kQuadsPerThread * lf2::kThreads || lds_cells > W)
         return hipErrorInvalidValue;
     const size_t lds = (size_t)lf2::lds_dwords(W, lds_cells) * 4u;
     if (lds > kLds) return hipErrorInvalidValue;
-    auto kern = &lf2::fermat_leaf2_kernel<C, TR>;
-    static bool attr = false;
-    if (!attr) {
+    auto kern = pack > 1u ? &lf2::fermat_leaf2_kernel<C, TR, true> : &lf2::fermat_leaf2_kernel<C, TR, false>;
+    static bool attr[2] = {false, false};
+    if (!attr[pack > 1u]) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds);
         if (e != hipSuccess) return e;
-        attr = true;
+        attr[pack > 1u] = true;
     }
-    const uint32_t grid = njobs < device_cus() ? njobs : device_cus();
+    const uint32_t npacks = (njobs + pack - 1u) / pack;
+    const uint32_t grid = npacks < device_cus() ? npacks : device_cus();
     hipLaunchKernelGGL(kern, dim3(grid), dim3(lf2::kThreads), lds, st, jobs, progs, steps, ops, x, cap, ord_mask,
-                       job_offset, njobs);
+                       job_offset, njobs, pack, slot_log2);
     return hipGetLastError();
 }
 

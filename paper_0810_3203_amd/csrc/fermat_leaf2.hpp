@@ -16,7 +16,10 @@
 //   * a workgroup runs many jobs in turn: while the butterflies of one job run
 //     in LDS, the cells of its next job are already being loaded into
 //     registers, and the outputs of a job leave LDS in the same sweep that
-//     stores the next job's inputs, so copies overlap compute within a CU.
+//     stores the next job's inputs, so copies overlap compute within a CU;
+//   * small leaves are packed: a workgroup takes `pack` consecutive jobs of the
+//     pass at once, job p in LDS cells [p slot, (p+1) slot), so that a pass of
+//     4-cell leaves still gives every wave a base case per step.
 // All device functions are inlined: LDS is reached only through ds_
 // instructions on the kernel's own allocation.
 #pragma once
@@ -35,20 +38,76 @@
 namespace tft {
 namespace lf2 {
 
+// The jobs a workgroup holds at once: jobs[first .. first + count), job p in
+// LDS cells [p << slot_log2, (p+1) << slot_log2).  PK = false: one job (count
+// = 1), its descriptor in scalar registers.  PK = true: lane p of every wave
+// keeps job p's cell range in registers, and the copy sweeps read a job's
+// range with lane reads instead of holding every job in scalar registers.
+template <bool PK>
+struct Pack {
+    uint32_t first, count;
+    Job j;                                                           // PK = false
+    uint32_t base_lo, base_hi, stride_lo, stride_hi, nload, nstore, prog, s;  // PK: job `lane` (lane < count)
+};
+
+template <bool PK>
+TFT_DINL Pack<PK> load_pack(const Job *__restrict__ jobs, uint32_t first, uint32_t count) {
+    Pack<PK> pk{first, count, Job{}, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    if constexpr (!PK) {
+        pk.j = jobs[first];
+    } else {
+        const uint32_t l = lane_id();
+        if (l < count) {
+            const Job J = jobs[first + l];
+            pk.base_lo = (uint32_t)J.base;
+            pk.base_hi = (uint32_t)(J.base >> 32);
+            pk.stride_lo = (uint32_t)J.stride;
+            pk.stride_hi = (uint32_t)(J.stride >> 32);
+            pk.nload = J.nload;
+            pk.nstore = J.nstore;
+            pk.prog = J.prog;
+            pk.s = J.s;
+        }
+    }
+    return pk;
+}
+
+// Cell range of pack cell c (wave-uniform): false if c belongs to no job or
+// lies at or beyond the job's input (out: output) cells.
+struct CellAt {
+    uint64_t base, stride;
+    uint32_t local;
+};
+template <bool PK>
+TFT_DINL bool pack_cell(const Pack<PK> &pk, uint32_t slot_log2, uint32_t c, bool out, CellAt &at) {
+    if constexpr (!PK) {
+        if (pk.count == 0u || c >= (out ? pk.j.nstore : pk.j.nload)) return false;
+        at.local = c;
+        at.base = pk.j.base;
+        at.stride = pk.j.stride;
+        return true;
+    } else {
+        const uint32_t p = c >> slot_log2;
+        if (p >= pk.count) return false;
+        at.local = c & ((1u << slot_log2) - 1u);
+        if (at.local >= (uint32_t)readlane(out ? pk.nstore : pk.nload, (int)p)) return false;
+        at.base = (uint64_t)readlane(pk.base_lo, (int)p) | (uint64_t)readlane(pk.base_hi, (int)p) << 32;
+        at.stride = (uint64_t)readlane(pk.stride_lo, (int)p) | (uint64_t)readlane(pk.stride_hi, (int)p) << 32;
+        return true;
+    }
+}
+
 template <int C, bool TR>
 struct QuadMap {
     static constexpr uint32_t W = 64u * C, K = quad_cells_per_sweep(C);
-    uint32_t c0;    // first cell of the thread
+    uint32_t c0;    // first cell of the thread (the same for the whole wave)
     uint32_t loff;  // LDS dword offset of the thread's quad inside its cell
     uint32_t goff;  // dword offset of the thread's quad inside a global cell
     TFT_DINL explicit QuadMap(uint32_t tid)
-        : c0(quad_c0(C, tid)), loff(quad_loff(C, TR, tid)), goff(quad_goff(C, TR, tid)) {}
-    // dword index (from x) of the thread's quad i of job J
-    TFT_DINL uint64_t global(const Job &J, int i) const {
-        return (J.base + (uint64_t)(c0 + (uint32_t)i * K) * J.stride) * W + goff;
-    }
+        : c0(uni(quad_c0(C, tid))), loff(quad_loff(C, TR, tid)), goff(quad_goff(C, TR, tid)) {}
+    // dword index (from x) of the thread's quad in the cell at
+    TFT_DINL uint64_t global(const CellAt &at) const { return (at.base + (uint64_t)at.local * at.stride) * W + goff; }
     TFT_DINL uint32_t lds(int i) const { return cell_base(W, c0 + (uint32_t)i * K) + loff; }
-    TFT_DINL bool valid(uint32_t ncells, int i) const { return c0 + (uint32_t)i * K < ncells; }
 };
 
 template <bool TR>
@@ -74,88 +133,179 @@ TFT_DINL u32x4 lds_get_quad(const uint32_t *sm, uint32_t a) {
     }
 }
 
-template <int C>
-TFT_DINL void run_prog(uint32_t *sm, const Job &J, const LeafProg *__restrict__ progs,
-                       const LeafStep *__restrict__ steps, const LeafOp *__restrict__ ops, uint32_t ord_mask,
-                       uint32_t wave) {
+// Runs the programs of every job of the pack, step by step; step st's base
+// cases of all the jobs are one list dealt out to the waves.
+template <int C, bool PK>
+TFT_DINL void run_pack(uint32_t *sm, const Job *__restrict__ jobs, const Pack<PK> &pk, uint32_t slot_log2,
+                       const LeafProg *__restrict__ progs, const LeafStep *__restrict__ steps,
+                       const LeafOp *__restrict__ ops, uint32_t ord_mask, uint32_t wave) {
+    constexpr uint32_t NW = kThreads / 64u;
     const Big<C> ar;
-    const LeafProg P = progs[J.prog];
-    for (uint32_t st = 0; st < P.step_count; ++st) {
-        const LeafStep LS = steps[P.step_begin + st];
-        for (uint32_t j = wave; j < LS.op_count; j += kThreads / 64u) base_case<C>(ar, sm, ops[LS.op_begin + j], J.s, ord_mask);
+    if constexpr (!PK) {
+        const LeafProg P = progs[pk.j.prog];
+        for (uint32_t st = 0; st < P.step_count; ++st) {
+            const LeafStep LS = steps[P.step_begin + st];
+            for (uint32_t j = wave; j < LS.op_count; j += NW) base_case<C>(ar, sm, ops[LS.op_begin + j], pk.j.s, ord_mask);
+            __syncthreads();
+        }
+        return;
+    }
+    // jobs of one program (the common case): one program, each step's items
+    // are (job, op) pairs dealt out in order
+    const uint32_t prog0 = uni(pk.prog);
+    if (ballot(lane_id() < pk.count && pk.prog != prog0) == 0ull) {
+        const LeafProg P = progs[prog0];
+        for (uint32_t st = 0; st < P.step_count; ++st) {
+            const LeafStep LS = steps[P.step_begin + st];
+            const uint32_t n = LS.op_count;
+            uint32_t p = 0, j = wave;
+            while (j >= n && p < pk.count) {
+                j -= n;
+                ++p;
+            }
+            while (p < pk.count) {
+                base_case<C>(ar, sm, ops[LS.op_begin + j], (uint32_t)readlane(pk.s, (int)p), ord_mask, p << slot_log2);
+                j += NW;
+                while (j >= n && p < pk.count) {
+                    j -= n;
+                    ++p;
+                }
+            }
+            __syncthreads();
+        }
+        return;
+    }
+    uint32_t nsteps = 0;
+    for (uint32_t p = 0; p < pk.count; ++p) {
+        const uint32_t sc = progs[jobs[pk.first + p].prog].step_count;
+        nsteps = sc > nsteps ? sc : nsteps;
+    }
+    for (uint32_t st = 0; st < nsteps; ++st) {
+        uint32_t off = 0;  // items of this step dealt so far
+        for (uint32_t p = 0; p < pk.count; ++p) {
+            const Job J = jobs[pk.first + p];
+            const LeafProg P = progs[J.prog];
+            if (st >= P.step_count) continue;
+            const LeafStep LS = steps[P.step_begin + st];
+            const uint32_t cofs = p << slot_log2;
+            for (uint32_t j = (wave + NW - off % NW) % NW; j < LS.op_count; j += NW)
+                base_case<C>(ar, sm, ops[LS.op_begin + j], J.s, ord_mask, cofs);
+            off += LS.op_count;
+        }
         __syncthreads();
     }
 }
 
-// One pass: jobs [job_begin, job_begin + njobs), a persistent grid of
-// workgroups of 512 threads, each running jobs blockIdx.x, blockIdx.x + gridDim.x, ...
-template <int C, bool TR>
+// One pass: jobs [job_begin, job_begin + njobs) in packs of `pack` consecutive
+// jobs (each in 2^slot_log2 LDS cells), a persistent grid of workgroups of 512
+// threads, each running packs blockIdx.x, blockIdx.x + gridDim.x, ...
+template <int C, bool TR, bool PK>
 __global__ void __launch_bounds__(512) fermat_leaf2_kernel(const Job *__restrict__ jobs,
                                                            const LeafProg *__restrict__ progs,
                                                            const LeafStep *__restrict__ steps,
                                                            const LeafOp *__restrict__ ops, uint32_t *__restrict__ x,
                                                            uint64_t cap, uint32_t ord_mask, uint32_t job_begin,
-                                                           uint32_t njobs) {
-    constexpr uint32_t W = 64u * C, WQ = W / 4u;
+                                                           uint32_t njobs, uint32_t pack, uint32_t slot_log2) {
+    constexpr uint32_t W = 64u * C;
     constexpr int QPT = kQuadsPerThread;
     extern __shared__ uint32_t sm[];
     const uint32_t tid = threadIdx.x;
     const uint32_t wave = uni(tid >> 6);
-    uint32_t jb = blockIdx.x;
-    if (jb >= njobs) return;
+    const uint32_t npacks = (njobs + pack - 1u) / pack;
+    uint32_t kb = blockIdx.x;
+    if (kb >= npacks) return;
+    jobs += job_begin;
     uint32_t *tops = x + cap * W;
+    auto pack_at = [&](uint32_t k) {
+        const uint32_t first = k * pack;
+        return load_pack<PK>(jobs, first, njobs - first < pack ? njobs - first : pack);
+    };
+    // top word of pack cell tid: its global index, or ~0 if the cell is not an
+    // input (out: not an output) of its job
+    auto top_index = [&](const Pack<PK> &pk, bool out) -> uint64_t {
+        if constexpr (!PK) {
+            if (pk.count == 0u) return ~0ull;
+            return tid < (out ? pk.j.nstore : pk.j.nload) ? pk.j.base + (uint64_t)tid * pk.j.stride : ~0ull;
+        } else {
+            const uint32_t p = tid >> slot_log2, local = tid & ((1u << slot_log2) - 1u);
+            if (p >= pk.count) return ~0ull;
+            const Job J = jobs[pk.first + p];
+            return local < (out ? J.nstore : J.nload) ? J.base + (uint64_t)local * J.stride : ~0ull;
+        }
+    };
+    const QuadMap<C, TR> qm(tid);
+    auto cell = [&](int i) { return qm.c0 + (uint32_t)i * QuadMap<C, TR>::K; };
 
     u32x4 pre[QPT];
     uint32_t pre_top = 0;
-    const QuadMap<C, TR> qm(tid);
-    Job J = jobs[job_begin + jb];
+    Pack<PK> pk = pack_at(kb);
+    {
 #pragma unroll
-    for (int i = 0; i < QPT; ++i)
-        if (qm.valid(J.nload, i)) pre[i] = *reinterpret_cast<const u32x4 *>(x + qm.global(J, i));
-    if (tid < J.nload) pre_top = tops[J.base + (uint64_t)tid * J.stride];
+        for (int i = 0; i < QPT; ++i) {
+            CellAt at;
+            if (pack_cell(pk, slot_log2, cell(i), false, at))
+                pre[i] = *reinterpret_cast<const u32x4 *>(x + qm.global(at));
+        }
+        const uint64_t ti = top_index(pk, false);
+        if (ti != ~0ull) pre_top = tops[ti];
 #pragma unroll
-    for (int i = 0; i < QPT; ++i)
-        if (qm.valid(J.nload, i)) lds_put_quad<TR>(sm, qm.lds(i), pre[i]);
-    if (tid < J.nload) sm[tid] = pre_top;
+        for (int i = 0; i < QPT; ++i) {
+            CellAt at;
+            if (pack_cell(pk, slot_log2, cell(i), false, at)) lds_put_quad<TR>(sm, qm.lds(i), pre[i]);
+        }
+        if (ti != ~0ull) sm[tid] = pre_top;
+    }
     __syncthreads();
 
     for (;;) {
-        const uint32_t jn = jb + gridDim.x;
-        const bool has_next = jn < njobs;
-        Job JN = J;
+        const uint32_t kn = kb + gridDim.x;
+        const bool has_next = kn < npacks;
+        Pack<PK> pn{0u, 0u, Job{}, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+        uint64_t tin = ~0ull;
         if (has_next) {
-            JN = jobs[job_begin + jn];
+            pn = pack_at(kn);
 #pragma unroll
-            for (int i = 0; i < QPT; ++i)
-                if (qm.valid(JN.nload, i)) pre[i] = *reinterpret_cast<const u32x4 *>(x + qm.global(JN, i));
-            if (tid < JN.nload) pre_top = tops[JN.base + (uint64_t)tid * JN.stride];
+            for (int i = 0; i < QPT; ++i) {
+                CellAt at;
+                if (pack_cell(pn, slot_log2, cell(i), false, at))
+                    pre[i] = *reinterpret_cast<const u32x4 *>(x + qm.global(at));
+            }
+            tin = top_index(pn, false);
+            if (tin != ~0ull) pre_top = tops[tin];
         }
 
-        run_prog<C>(sm, J, progs, steps, ops, ord_mask, wave);
+        run_pack<C, PK>(sm, jobs, pk, slot_log2, progs, steps, ops, ord_mask, wave);
 
-        // outputs of J leave LDS while the inputs of JN take their place; a
-        // thread reads and writes only its own quads, so no barrier between
-        const uint32_t nin = has_next ? JN.nload : 0u;
-        const uint32_t out_top = tid < J.nstore ? sm[tid] : 0u;
-        if (tid < nin) sm[tid] = pre_top;
+        // outputs of this pack leave LDS while the inputs of the next take their
+        // place; a thread reads and writes only its own quads, so no barrier between
+        const uint64_t tout = top_index(pk, true);
+        const uint32_t out_top = tout != ~0ull ? sm[tid] : 0u;
+        if (tin != ~0ull) sm[tid] = pre_top;
 #pragma unroll
         for (int i0 = 0; i0 < QPT; i0 += 4) {
             u32x4 out[4];
 #pragma unroll
-            for (int i = i0; i < i0 + 4; ++i)
-                if (qm.valid(J.nstore, i)) out[i - i0] = lds_get_quad<TR>(sm, qm.lds(i));
+            for (int i = i0; i < i0 + 4; ++i) {
+                CellAt at;
+                if (pack_cell(pk, slot_log2, cell(i), true, at)) out[i - i0] = lds_get_quad<TR>(sm, qm.lds(i));
+            }
 #pragma unroll
-            for (int i = i0; i < i0 + 4; ++i)
-                if (qm.valid(nin, i)) lds_put_quad<TR>(sm, qm.lds(i), pre[i]);
+            for (int i = i0; i < i0 + 4; ++i) {
+                CellAt at;
+                if (pack_cell(pn, slot_log2, cell(i), false, at)) lds_put_quad<TR>(sm, qm.lds(i), pre[i]);
+            }
 #pragma unroll
-            for (int i = i0; i < i0 + 4; ++i)
-                if (qm.valid(J.nstore, i)) *reinterpret_cast<u32x4 *>(x + qm.global(J, i)) = out[i - i0];
+            for (int i = i0; i < i0 + 4; ++i) {
+                CellAt at;
+                if (pack_cell(pk, slot_log2, cell(i), true, at))
+                    *reinterpret_cast<u32x4 *>(x + qm.global(at)) = out[i - i0];
+            }
         }
-        if (tid < J.nstore) tops[J.base + (uint64_t)tid * J.stride] = out_top;
+        if (tout != ~0ull) tops[tout] = out_top;
         if (!has_next) break;
         __syncthreads();
-        J = JN;
-        jb = jn;
+        pk = pn;
+        kb = kn;
     }
 }
 

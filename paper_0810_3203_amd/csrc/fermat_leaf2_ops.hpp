@@ -248,24 +248,6 @@ struct Big {
         for (int i = 0; i <= C; ++i) src[i] = ((uint32_t)i + row0 < (uint32_t)C ? pA : pB)[64 * i];
     }
 
-    // Low-part mask of limb j of this lane for a rotation by t bits: all ones
-    // for limbs below q = t / 32, pm for limb q, zero above.
-    struct Mask {
-        uint32_t full, isA, jq, pm;
-        TFT_DINL Mask(uint32_t l, uint32_t q, uint32_t pm_) {
-            const uint32_t qa = q / (uint32_t)C;
-            jq = q % (uint32_t)C;
-            pm = pm_;
-            full = l < qa ? ~0u : 0u;
-            isA = l == qa ? ~0u : 0u;
-        }
-        template <int J>
-        TFT_DINL uint32_t low() const {
-            const uint32_t S = (uint32_t)J < jq ? ~0u : ((uint32_t)J == jq ? pm : 0u);
-            return (isA & S) | full;
-        }
-    };
-
     // dst <- 2^e (x + t 2^N), x the element at src with top t (a canonical
     // residue): the rotation of x by t bits gives Lo - Hi (sign -1 if e >= N),
     // Lo the bits that stay below 2^N, Hi the bits that wrapped.
@@ -277,13 +259,24 @@ struct Big {
             uint32_t src[C + 1];
             rot_words(sm, es, rt.qp, src);
             wave_sync();  // every lane has read before any lane stores (es may be ed)
-            const Mask mk(l, rt.q, rt.pm);
+            // The wrapped part of limb j of lane l is r & M_j: M_j is all ones
+            // below the split limb q = qa C + jq, pm at it, zero above.  Lanes
+            // below qa wrap whole, lanes above not at all; lane qa takes M_j
+            // from lane j of a per-lane table, read as a wave-uniform value.
+            const uint32_t qa = rt.q / (uint32_t)C, jq = rt.q % (uint32_t)C;
+            uint32_t fv = l < qa ? ~0u : 0u, am = l == qa ? ~0u : 0u;
+            opaque(fv);  // plain words to the compiler: one and-or per limb, not a select
+            opaque(am);
+            const uint32_t stab = l < jq ? ~0u : (l == jq ? rt.pm : 0u);
             static_for<0, C>([&](auto jc) {
                 constexpr int j = decltype(jc)::value;
                 const uint32_t r = alignbit(src[j + 1], src[j], rt.c);
-                const uint32_t low = mk.template low<j>();
-                const uint32_t hp = r & low, lp = r & ~low;
-                v[j] = NEG ? subb(hp, lp, b) : subb(lp, hp, b);
+                uint32_t M = (am & readlane(stab, j)) | fv;  // one and-or, no select
+                opaque(M);                                    // formed once, used twice
+                // Lo - Hi with Lo = r & ~M, Hi = r & M: (r ^ M) - M, since
+                // r ^ M = Lo + (M - Hi); the negated form is M - (r ^ M)
+                const uint32_t x = r ^ M;
+                v[j] = NEG ? subb(M, x, b) : subb(x, M, b);
                 // groups of 8 limbs: the scheduler may not hoist every limb's
                 // shifts and masks ahead of the borrow chain (register pressure)
                 if constexpr ((j & 7) == 7) sched_barrier();
@@ -325,13 +318,17 @@ struct Big {
         uint32_t a[C], b[C];
         ld(sm, ei, a);
         ld(sm, ej, b);
-        {
-            uint32_t d[C];
-            const uint32_t bd = chain_sub(d, a, b);
-            finish<true>(sm, d, bd, ti - tj, 0, 0u, ej, ij);
+        // the sum and difference chains interleaved limb by limb, in place: two
+        // independent carries, so neither chain waits on its own carry
+        uint32_t cy = 0, bd = 0;
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const uint32_t t = a[j];
+            a[j] = addc(t, b[j], cy);
+            b[j] = subb(t, b[j], bd);
         }
+        finish<true>(sm, b, bd, ti - tj, 0, 0u, ej, ij);
         sched_barrier();
-        const uint32_t cy = chain_add(a, a, b);
         finish<false>(sm, a, cy, ti + tj, 0, 0u, ei, ii);
     }
     // xi <- xi + xj (i = j doubles)
@@ -397,11 +394,13 @@ TFT_DINL uint32_t base_case_steps(uint32_t code) {
 }
 
 // One base case (opcode, cells i0 and i1, exponent (s 2^alog + b) mod 2N of
-// the job's twist s) on the leaf in LDS, run by one wave.
+// the job's twist s) on the leaf in LDS, run by one wave; the job's cells start
+// at LDS cell cofs.
 template <int C>
-TFT_DINL void base_case(const Big<C> &ar, uint32_t *sm, const LeafOp &o, uint32_t s, uint32_t ord_mask) {
+TFT_DINL void base_case(const Big<C> &ar, uint32_t *sm, const LeafOp &o, uint32_t s, uint32_t ord_mask,
+                        uint32_t cofs = 0u) {
     constexpr uint32_t W = Big<C>::W;
-    const uint32_t i01[2] = {(o.w0 >> 4) & 16383u, (o.w0 >> 18) & 16383u};
+    const uint32_t i01[2] = {((o.w0 >> 4) & 16383u) + cofs, ((o.w0 >> 18) & 16383u) + cofs};
     const uint32_t ex = (uint32_t)((((uint64_t)s << (o.w1 >> 24)) + (uint64_t)(o.w1 & 0xFFFFFFu)) & ord_mask);
     const uint32_t exs[3] = {ex, (0u - ex) & ord_mask, ord_mask};  // e, -e, 2N - 1 (2^(2N-1) = 1/2)
     for (uint32_t seq = base_case_steps(o.w0 & 15u); seq != 0u; seq >>= 8) {
