@@ -277,29 +277,26 @@ __global__ void __launch_bounds__(512) fermat_leaf2_kernel(const Job *__restrict
         run_pack<C, PK>(sm, jobs, pk, slot_log2, progs, steps, ops, ord_mask, wave);
 
         // outputs of this pack leave LDS while the inputs of the next take their
-        // place; a thread reads and writes only its own quads, so no barrier between
+        // place; a thread reads and writes only its own quads, so no barrier
+        // between.  First every quad is swapped (LDS output into the register
+        // the input leaves), then all global stores follow: the LDS writes
+        // wait for the prefetched loads only, never for a store of the same
+        // sweep (both count in vmcnt).
         const uint64_t tout = top_index(pk, true);
         const uint32_t out_top = tout != ~0ull ? sm[tid] : 0u;
         if (tin != ~0ull) sm[tid] = pre_top;
 #pragma unroll
-        for (int i0 = 0; i0 < QPT; i0 += 4) {
-            u32x4 out[4];
+        for (int i = 0; i < QPT; ++i) {
+            CellAt at;
+            u32x4 o = pre[i];
+            if (pack_cell(pk, slot_log2, cell(i), true, at)) o = lds_get_quad<TR>(sm, qm.lds(i));
+            if (pack_cell(pn, slot_log2, cell(i), false, at)) lds_put_quad<TR>(sm, qm.lds(i), pre[i]);
+            pre[i] = o;
+        }
 #pragma unroll
-            for (int i = i0; i < i0 + 4; ++i) {
-                CellAt at;
-                if (pack_cell(pk, slot_log2, cell(i), true, at)) out[i - i0] = lds_get_quad<TR>(sm, qm.lds(i));
-            }
-#pragma unroll
-            for (int i = i0; i < i0 + 4; ++i) {
-                CellAt at;
-                if (pack_cell(pn, slot_log2, cell(i), false, at)) lds_put_quad<TR>(sm, qm.lds(i), pre[i]);
-            }
-#pragma unroll
-            for (int i = i0; i < i0 + 4; ++i) {
-                CellAt at;
-                if (pack_cell(pk, slot_log2, cell(i), true, at))
-                    *reinterpret_cast<u32x4 *>(x + qm.global(at)) = out[i - i0];
-            }
+        for (int i = 0; i < QPT; ++i) {
+            CellAt at;
+            if (pack_cell(pk, slot_log2, cell(i), true, at)) *reinterpret_cast<u32x4 *>(x + qm.global(at)) = pre[i];
         }
         if (tout != ~0ull) tops[tout] = out_top;
         if (!has_next) break;

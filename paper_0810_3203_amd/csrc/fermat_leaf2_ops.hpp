@@ -241,11 +241,15 @@ struct Big {
     // Words of the element at cell offset e rotated down by qp limbs:
     // src[i] = limb (l C - qp + i) mod W, i = 0..C.
     TFT_DINL void rot_words(const uint32_t *sm, uint32_t e, uint32_t qp, uint32_t (&src)[C + 1]) const {
-        const uint32_t row0 = uni(rot_row0(C, qp));
-        const uint32_t *pA = sm + rot_base_a(C, e, l, qp);
-        const uint32_t *pB = sm + rot_base_b(C, e, l, qp);  // e >= W keeps this inside the allocation
+        const uint32_t sA = uni((uint32_t)C - rot_row0(C, qp));  // words [0, sA) come from base A
+        // LDS byte addresses of the two bases, selected per word (the word's
+        // own offset is the load's immediate); e >= W keeps base B inside the
+        // allocation
+        uint32_t bA = lds_addr(sm) + 4u * rot_base_a(C, e, l, qp), bB = lds_addr(sm) + 4u * rot_base_b(C, e, l, qp);
+        opaque(bA);
+        opaque(bB);
 #pragma unroll
-        for (int i = 0; i <= C; ++i) src[i] = ((uint32_t)i + row0 < (uint32_t)C ? pA : pB)[64 * i];
+        for (int i = 0; i <= C; ++i) src[i] = lds_word(sm, ((uint32_t)i < sA ? bA : bB) + 256u * (uint32_t)i);
     }
 
     // dst <- 2^e (x + t 2^N), x the element at src with top t (a canonical

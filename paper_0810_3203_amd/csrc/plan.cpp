@@ -7,6 +7,19 @@
 namespace tft {
 namespace {
 
+// l1 of a sub-transform of length 2^lg (Alg. 1 / Alg. 2 split 2^l1 x 2^(lg-l1)):
+// the top level takes the chosen split (0: the paper's, lg/2); below it, a
+// transform of at most two leaves' levels keeps its columns one whole leaf
+// (rows get the remainder), so passes are whole leaves but one; deeper ones
+// are halved.  Every split gives the same outputs.
+uint32_t sub_split_l1(uint32_t lg, bool top, uint32_t top_l1, uint32_t leaf_log2) {
+    if (top_l1 == kSplitDC) return 1;
+    if (top && top_l1 && top_l1 < lg) return top_l1;
+    if (top) return lg / 2;
+    if (lg <= 2 * leaf_log2) return leaf_log2;
+    return lg / 2;
+}
+
 struct SymOp {
     uint32_t code, i0, i1, alog, b;
 };
@@ -166,11 +179,7 @@ struct Builder {
         passes[p].push_back({base, stride, prog, (uint32_t)(s % ord), (uint32_t)nload, (uint32_t)nstore});
     }
 
-    uint32_t split_l1(uint32_t lg, bool top) const {
-        if (top_l1 == kSplitDC) return 1;
-        if (top && top_l1 && top_l1 < lg) return top_l1;
-        return lg / 2;
-    }
+    uint32_t split_l1(uint32_t lg, bool top) const { return sub_split_l1(lg, top, top_l1, leaf_log2); }
 
     // Alg. 1 on the view (base, stride) of length 2^lg, starting at pass p;
     // returns the first pass after it.
@@ -237,11 +246,7 @@ struct PassCounter {
     uint32_t leaf_log2, top_l1;
     std::map<std::tuple<uint32_t, uint64_t, uint64_t, uint32_t, bool>, uint32_t> memo;
 
-    uint32_t l1_of(uint32_t lg, bool top) const {
-        if (top_l1 == kSplitDC) return 1;
-        if (top && top_l1 && top_l1 < lg) return top_l1;
-        return lg / 2;
-    }
+    uint32_t l1_of(uint32_t lg, bool top) const { return sub_split_l1(lg, top, top_l1, leaf_log2); }
     uint32_t tft(uint32_t lg, uint64_t z, uint64_t n, bool top) {
         if (lg <= leaf_log2) return 1;
         auto key = std::make_tuple(lg, z, n, 0u, top);

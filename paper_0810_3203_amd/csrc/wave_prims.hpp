@@ -23,6 +23,10 @@ inline uint32_t alignbit(uint32_t hi, uint32_t lo, uint32_t s) {
 }
 inline uint32_t opaque_zero() { return 0u; }
 inline void opaque(uint32_t &) {}
+// LDS words by byte address: the emulation's addresses are byte offsets from
+// the start of the array
+inline uint32_t lds_addr(const uint32_t *) { return 0u; }
+inline uint32_t lds_word(const uint32_t *sm, uint32_t byte_addr) { return sm[byte_addr / 4u]; }
 inline void sched_barrier() {}
 // LDS written by some lanes and then read by others of the same wave: a
 // wavefront executes each instruction for all lanes, the emulation has to wait
@@ -66,6 +70,14 @@ TFT_DINL uint32_t opaque_zero() {
 // (x - borrow) into the next chain's first addition of the same limb as
 // x + (-borrow) + carry, which has the right sum but the wrong carry out.
 TFT_DINL void opaque(uint32_t &x) { asm volatile("" : "+v"(x)); }
+// LDS words by byte address in the workgroup's LDS: an address chosen per lane
+// at run time feeds a ds_read directly, with the word's constant offset in the
+// instruction's immediate field.
+typedef __attribute__((address_space(3))) const uint32_t lds_cu32;
+TFT_DINL uint32_t lds_addr(const uint32_t *sm) {
+    return (uint32_t)(uintptr_t)(lds_cu32 *)sm;
+}
+TFT_DINL uint32_t lds_word(const uint32_t *, uint32_t byte_addr) { return *(lds_cu32 *)(uintptr_t)byte_addr; }
 TFT_DINL void sched_barrier() { __builtin_amdgcn_sched_barrier(0); }
 // a wavefront runs every lane through each instruction in order: nothing to do
 TFT_DINL void wave_sync() {}
