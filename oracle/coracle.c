@@ -8,6 +8,8 @@
  *   co_fermat_dft_sampled  eq. (1) of Sect. 2 in R = Z/(2^N+1), theta = 2:
  *                          a_hat_j = zeta^(j') sum_{i<z} omega_L^(i j') a_i, at listed j.
  *   co_nega_dft_sampled    eq. (1) in R = (Z/mZ)[y]/(y^K+1), theta = y (Sect. 5.2).
+ *   co_prime_dft_sampled   eq. (1) in R = Z/pZ, theta of order ord (Sect. 6): the
+ *                          sum by Horner's rule at x = omega_L^(j'), times zeta^(j').
  *   co_zx_coeffs           u_k = sum_i g_i h_{k-i} over Z (schoolbook, Sect. 5.1).
  *   co_zmx_coeffs          u_k = sum_i g_i h_{k-i} mod m (schoolbook, Sect. 5.2).
  *   co_fingerprint         sum_k c_k r^k mod P (for Schwartz-Zippel checks).
@@ -285,6 +287,71 @@ int co_nega_dft_sampled(uint32_t K, uint64_t m, uint32_t L, uint64_t s, uint64_t
         J->j1 = nj * (t + 1) / nthreads;
     }
     run_threads(jobs, sizeof(ndft_job), nthreads, ndft_worker);
+    free(jobs);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* eq. (1) in Z/pZ                                                     */
+/* ------------------------------------------------------------------ */
+
+static uint64_t powmod(uint64_t b, uint64_t e, uint64_t p) {
+    uint64_t r = 1 % p;
+    b %= p;
+    while (e) {
+        if (e & 1) r = (uint64_t)((u128)r * b % p);
+        b = (uint64_t)((u128)b * b % p);
+        e >>= 1;
+    }
+    return r;
+}
+
+typedef struct {
+    uint64_t p, theta, ord, s, z;
+    uint32_t L, l;
+    const uint32_t *a;
+    const uint64_t *js;
+    uint32_t *out;
+    uint64_t j0, j1;
+} pdft_job;
+
+static void *pdft_worker(void *arg) {
+    pdft_job *J = arg;
+    for (uint64_t jj = J->j0; jj < J->j1; jj++) {
+        const uint64_t jr = bitrev32((uint32_t)J->js[jj], J->l);
+        const uint64_t x = powmod(J->theta, (J->ord / J->L) * jr % J->ord, J->p);
+        uint64_t acc = 0;
+        for (uint64_t i = J->z; i-- > 0;) acc = (uint64_t)(((u128)acc * x + J->a[i]) % J->p);
+        const uint64_t zj = powmod(J->theta, (J->s % J->ord) * jr % J->ord, J->p);
+        J->out[jj] = (uint32_t)((u128)acc * zj % J->p);
+    }
+    return NULL;
+}
+
+int co_prime_dft_sampled(uint64_t p, uint64_t theta, uint64_t ord, uint32_t L, uint64_t s, uint64_t z,
+                         const uint32_t *a, uint64_t nj, const uint64_t *js, uint32_t *out, int nthreads) {
+    if (L < 1 || (L & (L - 1)) || ord % L || p < 3 || p >= (1ull << 32)) return 1;
+    uint32_t l = 0;
+    while ((1u << l) < L) l++;
+    if (nthreads < 1) nthreads = 1;
+    if ((uint64_t)nthreads > nj) nthreads = nj ? (int)nj : 1;
+    pdft_job *jobs = calloc(nthreads, sizeof(pdft_job));
+    for (int t = 0; t < nthreads; t++) {
+        pdft_job *J = &jobs[t];
+        J->p = p;
+        J->theta = theta;
+        J->ord = ord;
+        J->s = s;
+        J->z = z;
+        J->L = L;
+        J->l = l;
+        J->a = a;
+        J->js = js;
+        J->out = out;
+        J->j0 = nj * t / nthreads;
+        J->j1 = nj * (t + 1) / nthreads;
+    }
+    run_threads(jobs, sizeof(pdft_job), nthreads, pdft_worker);
     free(jobs);
     return 0;
 }

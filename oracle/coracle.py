@@ -38,6 +38,8 @@ def load():
         lib.co_fermat_mul2exp.restype = I
         lib.co_nega_dft_sampled.argtypes = [U32, U64, U32, U64, U64, P, U64, P, P, I]
         lib.co_nega_dft_sampled.restype = I
+        lib.co_prime_dft_sampled.argtypes = [U64, U64, U64, U32, U64, U64, P, U64, P, P, I]
+        lib.co_prime_dft_sampled.restype = I
         lib.co_zx_coeffs.argtypes = [P, U64, U32, P, U64, U32, P, U64, P, U32, I]
         lib.co_zx_coeffs.restype = I
         lib.co_zmx_coeffs.argtypes = [P, U64, P, U64, U64, P, U64, P, I]
@@ -75,6 +77,19 @@ def fermat_dft_sampled(N, L, s, limbs, tops, js, nthreads=None):
     if rc:
         raise ValueError("co_fermat_dft_sampled: bad arguments")
     return out_l, out_t
+
+
+def prime_dft_sampled(ring, L, s, a, js, nthreads=None):
+    """Eq. (1) in Z/pZ (ring: tft_oracle.PrimeRing) at indices js; a: uint32 values."""
+    lib = load()
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    js = np.ascontiguousarray(js, dtype=np.uint64)
+    out = np.zeros(len(js), dtype=np.uint32)
+    rc = lib.co_prime_dft_sampled(ring.p, ring.theta, ring.ord, L, s, len(a), _ptr(a), len(js), _ptr(js),
+                                  _ptr(out), _threads(nthreads))
+    if rc:
+        raise ValueError("co_prime_dft_sampled: bad arguments")
+    return out
 
 
 def fermat_mul2exp(N, limbs, top, e):

@@ -1,10 +1,12 @@
 """Plain Python oracle (exact integers) — test infrastructure only.
 
 Follows the paper's Sect. 2 ("Notation and setup"):
-  * the ring R with a principal root of unity, here either
-      Z/(2^N+1) with theta = 2 of order 2N       (the Schoenhage-Strassen ring), or
+  * the ring R with a principal root of unity, here
+      Z/(2^N+1) with theta = 2 of order 2N       (the Schoenhage-Strassen ring),
       (Z/mZ)[y]/(y^K+1) with theta = y of order 2K (the Schoenhage-Nussbaumer ring,
-                                                   Sect. 5.2);
+                                                   Sect. 5.2), or
+      Z/pZ, p a word-size prime, with theta of order the largest power of two
+      dividing p - 1                            (the small-coefficient case, Sect. 6);
   * omega_L = theta^(ord/L), the principal L-th root (compatibility relation);
   * the weighted DFT, eq. (1), outputs in bit-reversed order;
   * TFT(L, zeta, z, n) = first n outputs of eq. (1) with a_i = 0 for i >= z;
@@ -163,6 +165,72 @@ class NegaRing:
 
     def eq(self, a, b):
         return self.canon(a) == self.canon(b)
+
+
+class PrimeRing:
+    """R = Z/pZ, p an odd prime, with theta = r^((p-1)/2^v): r the smallest
+    primitive root mod p and 2^v the largest power of two dividing p - 1, so
+    theta has order exactly 2^v (the word-size coefficient ring of Sect. 6).
+    Elements are ints in [0, p)."""
+
+    kind = "prime"
+
+    def __init__(self, p: int):
+        if p < 3 or p % 2 == 0 or any(p % q == 0 for q in range(3, int(p ** 0.5) + 1, 2)):
+            raise ValueError("p must be an odd prime")
+        self.p = p
+        v = 0
+        while (p - 1) % (2 << v) == 0:
+            v += 1
+        self.ord = 1 << v
+        self.r = self._primitive_root()
+        self.theta = pow(self.r, (p - 1) >> v, p)
+
+    def _primitive_root(self):
+        p = self.p
+        n, qs, q = p - 1, [], 2
+        while q * q <= n:
+            if n % q == 0:
+                qs.append(q)
+                while n % q == 0:
+                    n //= q
+            q += 1
+        if n > 1:
+            qs.append(n)
+        for r in range(2, p):
+            if all(pow(r, (p - 1) // q, p) != 1 for q in qs):
+                return r
+        raise ValueError("no primitive root")
+
+    def zero(self):
+        return 0
+
+    def canon(self, x):
+        return int(x) % self.p
+
+    def add(self, a, b):
+        return (a + b) % self.p
+
+    def sub(self, a, b):
+        return (a - b) % self.p
+
+    def mul(self, a, b):
+        return a * b % self.p
+
+    def scal(self, a, k: int):
+        return a * k % self.p
+
+    def theta_pow(self, e: int):
+        return pow(self.theta, e % self.ord, self.p)
+
+    def mul_theta(self, a, e: int):
+        return a * self.theta_pow(e) % self.p
+
+    def inv_pow2(self, k: int):
+        return pow(2, -k, self.p)
+
+    def eq(self, a, b):
+        return a % self.p == b % self.p
 
 
 def omega_exp(ring, L: int) -> int:

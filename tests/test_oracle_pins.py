@@ -23,25 +23,30 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
 def _rand_elem(ring, rng):
-    if ring.kind == "fermat":
+    if ring.kind in ("fermat", "prime"):
         return rng.randrange(ring.p)
     return tuple(rng.randrange(ring.m) for _ in range(ring.K))
 
 
 def _theta(ring):
+    if ring.kind == "prime":
+        return ring.theta
     return 2 if ring.kind == "fermat" else tuple(1 if i == 1 else 0 for i in range(ring.K))
 
 
 def _one(ring):
-    return 1 if ring.kind == "fermat" else tuple(1 if i == 0 else 0 for i in range(ring.K))
+    return 1 if ring.kind in ("fermat", "prime") else tuple(1 if i == 0 else 0 for i in range(ring.K))
 
 
 def _neg_one(ring):
-    return ring.p - 1 if ring.kind == "fermat" else tuple(ring.m - 1 if i == 0 else 0 for i in range(ring.K))
+    if ring.kind in ("fermat", "prime"):
+        return ring.p - 1
+    return tuple(ring.m - 1 if i == 0 else 0 for i in range(ring.K))
 
 
 RINGS = [O.FermatRing(2), O.FermatRing(4), O.FermatRing(8), O.FermatRing(64), O.FermatRing(96),
-         O.NegaRing(4, 15), O.NegaRing(8, (1 << 61) + 11)]
+         O.NegaRing(4, 15), O.NegaRing(8, (1 << 61) + 11), O.PrimeRing(17), O.PrimeRing(97), O.PrimeRing(257)]
+WORD_PRIME = 15 * (1 << 27) + 1
 
 
 # ---------------------------------------------------------------------------
@@ -181,7 +186,8 @@ def test_tft_is_prefix_of_dft_with_zero_tail():
 # closed-form base cases (Alg. 1 and Alg. 2 at L = 2)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("ring", [O.FermatRing(8), O.FermatRing(64), O.NegaRing(4, 15)], ids=["z257", "f64", "nega"])
+@pytest.mark.parametrize("ring", [O.FermatRing(8), O.FermatRing(64), O.NegaRing(4, 15), O.PrimeRing(97)],
+                         ids=["z257", "f64", "nega", "p97"])
 def test_tft_base_case_closed_forms(ring):
     rng = random.Random(11)
     for s in range(0, ring.ord, max(1, ring.ord // 8)):
@@ -193,7 +199,8 @@ def test_tft_base_case_closed_forms(ring):
         assert O.tft(ring, 2, s, 1, 1, [x0]) == [x0]
 
 
-@pytest.mark.parametrize("ring", [O.FermatRing(8), O.FermatRing(64), O.NegaRing(4, 15)], ids=["z257", "f64", "nega"])
+@pytest.mark.parametrize("ring", [O.FermatRing(8), O.FermatRing(64), O.NegaRing(4, 15), O.PrimeRing(97)],
+                         ids=["z257", "f64", "nega", "p97"])
 def test_itft_base_case_closed_forms(ring):
     """itft_case's expected output equals Alg. 2's base-case formulas applied to its inputs."""
     rng = random.Random(12)
@@ -251,7 +258,8 @@ def test_itft_unique_bruteforce_z5():
 # the product in R[X] (Sect. 2) and schoolbook products
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("ring", [O.FermatRing(64), O.NegaRing(8, 1000003)], ids=["f64", "nega"])
+@pytest.mark.parametrize("ring", [O.FermatRing(64), O.NegaRing(8, 1000003), O.PrimeRing(WORD_PRIME)],
+                         ids=["f64", "nega", "wordprime"])
 def test_convolution_identity(ring):
     """TFT of the schoolbook product = pointwise product of the TFTs (first n values)."""
     rng = random.Random(5)
@@ -264,6 +272,33 @@ def test_convolution_identity(ring):
         lhs = O.tft(ring, L, 0, n, n, u)
         rhs = O.pointwise(ring, O.tft(ring, L, 0, lg, n, g), O.tft(ring, L, 0, lh, n, h))
         assert lhs == rhs
+
+
+def test_word_prime_ring_facts():
+    """p = 15 2^27 + 1 is prime, 31 is its smallest primitive root, theta = 31^15
+    has order exactly 2^27 (Sect. 6: roots of unity of every power-of-two order
+    up to 2^27 exist in Z/pZ)."""
+    p = WORD_PRIME
+    assert all(p % q for q in range(2, 44900))  # 44900^2 > p
+    ring = O.PrimeRing(p)
+    assert ring.ord == 1 << 27 and ring.r == 31
+    assert all(pow(31, (p - 1) // q, p) != 1 for q in (2, 3, 5)) and all(pow(r, (p - 1) // 2, p) == 1 or
+                                                                        pow(r, (p - 1) // 3, p) == 1 or
+                                                                        pow(r, (p - 1) // 5, p) == 1
+                                                                        for r in range(2, 31))
+    assert ring.theta == pow(31, 15, p)
+    assert pow(ring.theta, 1 << 26, p) == p - 1 and pow(ring.theta, 1 << 27, p) == 1
+    assert ring.inv_pow2(1) * 2 % p == 1
+
+
+def test_word_prime_schoolbook_against_numpy_convolve():
+    rng = random.Random(21)
+    ring = O.PrimeRing(WORD_PRIME)
+    for lg, lh in [(1, 1), (7, 3), (40, 33)]:
+        g = [rng.randrange(ring.p) for _ in range(lg)]
+        h = [rng.randrange(ring.p) for _ in range(lh)]
+        want = [int(v) % ring.p for v in np.convolve(np.array(g, dtype=object), np.array(h, dtype=object))]
+        assert O.rx_mul_schoolbook(ring, g, h) == want
 
 
 def test_zx_mul_against_python_bigint_kronecker():
@@ -405,6 +440,16 @@ def _pins_pass():
     except AssertionError:
         return False
     return True
+
+
+def test_c_prime_dft_matches_python(coracle):
+    ring = O.PrimeRing(WORD_PRIME)
+    rng = random.Random(23)
+    for L, s, z in [(2, 0, 2), (16, 3, 11), (256, 12345, 200)]:
+        a = [rng.randrange(ring.p) for _ in range(z)]
+        js = list(range(L)) if L <= 16 else [0, 1, 7, 100, 255]
+        got = [int(v) for v in coracle.prime_dft_sampled(ring, L, s, np.array(a, dtype=np.uint32), js)]
+        assert got == O.dft_eq1(ring, L, s, a, js)
 
 
 def test_pins_pass_unmutated():
