@@ -58,13 +58,19 @@ typedef enum {
     TFT_E_UNSUPPORTED = 6  /* valid request outside what this build implements */
 } tft_status;
 
-enum { TFT_RING_FERMAT = 1, TFT_RING_NEGA = 2 };
+enum { TFT_RING_FERMAT = 1, TFT_RING_NEGA = 2, TFT_RING_PRIME = 3 };
+#define TFT_PRIME_P 2013265921u /* 15 * 2^27 + 1 */
 
 /* The coefficient ring R of Sect. 2.
  *   kind = TFT_RING_FERMAT: R = Z/(2^N+1), theta = 2 of order 2N (Sect. 2 example,
  *          Sect. 5.1).  This build needs N = 32*W with W a power of two, 1 <= W <= 4096.
  *   kind = TFT_RING_NEGA:   R = (Z/mZ)[y]/(y^K+1), theta = y of order 2K (Sect. 5.2).
  *          This build needs K a power of two, 2 <= K <= 4096, and m odd, 3 <= m < 2^62.
+ *   kind = TFT_RING_PRIME:  R = Z/pZ with the word-size prime p = m = TFT_PRIME_P
+ *          (the small-coefficient case, Sect. 6), theta = 31^15 of order 2^27 (31 is
+ *          the smallest primitive root mod p).  A cell is one uint32 residue in
+ *          [0, p); an array of C cells is C uint32 (4 C bytes).  Inputs must be
+ *          canonical.  No other prime in this build.
  * Unused fields must be zero. */
 typedef struct {
     uint32_t kind;
@@ -266,6 +272,23 @@ int zmx_mul_nussbaumer_workspace(uint64_t len_g, uint64_t len_h, uint32_t log2K,
  *   out    len_g + len_h - 1 coefficients (uint64, in [0, m)). */
 int zmx_mul_nussbaumer(const uint64_t *g, uint64_t len_g, const uint64_t *h, uint64_t len_h, uint64_t m,
                        uint32_t log2K, uint64_t *out, void *ws, uint64_t ws_bytes, void *stream);
+
+/* Workspace bytes zpx_mul_ntt needs: two cell arrays of the transform length. */
+int zpx_mul_ntt_workspace(uint64_t len_g, uint64_t len_h, uint64_t *bytes);
+
+/* Product u = g h in (Z/pZ)[x], p = TFT_PRIME_P, through TFT(g), TFT(h), n
+ * pointwise products and the ITFT over R = Z/pZ (Sect. 2; the small-coefficient
+ * case of Sect. 6), n = len_g + len_h - 1, transform length 2^l the smallest
+ * power of two >= n, l <= 24 (else TFT_E_ARG).
+ *   g, h      len_g, len_h coefficients (uint32, each < p), device memory.
+ *   pad_rows  0: transforms truncated at n; 1: n rounded up to whole rows of
+ *             the paper's split (L2 = 2^(l - floor(l/2))), Sect. 6's zero-padding
+ *             that leaves the ITFT without a partial row.  Same output.
+ *   out       n coefficients (uint32, in [0, p)).
+ *   ws        zpx_mul_ntt_workspace bytes.
+ * The first call with a new shape builds and uploads its plans. */
+int zpx_mul_ntt(const uint32_t *g, uint64_t len_g, const uint32_t *h, uint64_t len_h, uint32_t pad_rows,
+                uint32_t *out, void *ws, uint64_t ws_bytes, void *stream);
 
 /* ---- batches of independent Z[x] products ---- */
 

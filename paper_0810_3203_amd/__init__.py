@@ -13,6 +13,8 @@ from ._binding import (  # noqa: F401
     POLICY_GIVEN,
     POLICY_MODEL,
     POLICY_RULE,
+    PRIME,
+    PRIME_P,
     SPLIT_DC,
     SS_FEATURES,
     STATIC_SCRATCH_BYTES,
@@ -31,6 +33,7 @@ from ._binding import (  # noqa: F401
     lib_path,
     nega_ring,
     pointwise_mul,
+    prime_ring,
     requests_array,
     ring_check,
     ss_candidates,
@@ -47,6 +50,7 @@ from ._binding import (  # noqa: F401
     zx_mul_ss_timed,
     zx_mul_ss_workspace,
     zx_request,
+    zpx_mul_ntt,
     ZXRequest,
 )
 
@@ -57,4 +61,5 @@ __all__ = [
     "BatchPlan", "MLP", "SPLIT_DC", "SS_FEATURES", "ZXRequest", "requests_array", "ss_candidates", "ss_default_params",
     "ss_features", "ss_time", "zx_request", "POLICY_GIVEN", "POLICY_RULE", "POLICY_MODEL", "transform_workspace",
     "STATIC_SCRATCH_BYTES", "zx_mul_ss_static", "alu_rate",
+    "PRIME", "PRIME_P", "prime_ring", "zpx_mul_ntt",
 ]

@@ -12,6 +12,8 @@ lib_path = os.path.join(HERE, "libtft.so")
 
 FERMAT = 1
 NEGA = 2
+PRIME = 3
+PRIME_P = 15 * (1 << 27) + 1  # the word-size prime of the Z/pZ ring
 
 _STATUS_NAMES = {0: "TFT_OK", 1: "TFT_E_ARG", 2: "TFT_E_RING", 3: "TFT_E_RANGE", 4: "TFT_E_WORKSPACE",
                  5: "TFT_E_DEVICE", 6: "TFT_E_UNSUPPORTED"}
@@ -75,6 +77,11 @@ def nega_ring(K: int, m: int) -> Ring:
     return Ring(NEGA, 0, K, 0, m)
 
 
+def prime_ring() -> Ring:
+    """Z/pZ, p = 15 2^27 + 1 (the small-coefficient ring; cells are uint32 residues)."""
+    return Ring(PRIME, 0, 0, 0, PRIME_P)
+
+
 _lib = None
 
 
@@ -122,6 +129,10 @@ def lib():
         L.zx_mul_ss_timed.restype = I
         L.zmx_mul_nussbaumer_workspace.argtypes = [U64, U64, U32, ctypes.POINTER(U64)]
         L.zmx_mul_nussbaumer_workspace.restype = I
+        L.zpx_mul_ntt_workspace.argtypes = [U64, U64, ctypes.POINTER(U64)]
+        L.zpx_mul_ntt_workspace.restype = I
+        L.zpx_mul_ntt.argtypes = [P, U64, P, U64, U32, P, P, U64, P]
+        L.zpx_mul_ntt.restype = I
         L.zmx_mul_nussbaumer.argtypes = [P, U64, P, U64, U64, U32, P, P, U64, P]
         L.zmx_mul_nussbaumer.restype = I
         L.tft_plan_create.argtypes = [RP, U32, U32, U64, U64, U64, U32, ctypes.POINTER(Split), ctypes.POINTER(P)]
@@ -333,6 +344,19 @@ def zmx_mul_nussbaumer(g, h, m, log2K, out, ws=None, stream=None):
         ws = torch.empty(need, dtype=torch.uint8, device=g.device)
     _check(lib().zmx_mul_nussbaumer(_ptr(g), len_g, _ptr(h), len_h, m, log2K, _ptr(out), _ptr(ws),
                                     ws.numel() * ws.element_size(), _stream(stream)), "zmx_mul_nussbaumer")
+    return out
+
+
+def zpx_mul_ntt(g, h, out, pad_rows=0, ws=None, stream=None):
+    """u = g h in (Z/pZ)[x] (p = PRIME_P); g, h, out: int32 device tensors of residues."""
+    len_g, len_h = g.numel(), h.numel()
+    if ws is None:
+        import torch
+        need = ctypes.c_uint64(0)
+        _check(lib().zpx_mul_ntt_workspace(len_g, len_h, ctypes.byref(need)), "zpx_mul_ntt_workspace")
+        ws = torch.empty(need.value, dtype=torch.uint8, device=g.device)
+    _check(lib().zpx_mul_ntt(_ptr(g), len_g, _ptr(h), len_h, pad_rows, _ptr(out), _ptr(ws),
+                             ws.numel() * ws.element_size(), _stream(stream)), "zpx_mul_ntt")
     return out
 
 

@@ -19,7 +19,7 @@ BUILD = os.path.join(os.path.dirname(HERE), "_build")
 ARCH = os.environ.get("TFT_OFFLOAD_ARCH", "gfx950")
 
 DEVICE_SOURCES = ["fermat.hip", "fermat_leaf_p.hip", "fermat_leaf_t.hip", "fermat_leaf2.hip", "nega.hip", "mlp.hip", "ss_static.hip",
-                  "alu_rate.hip"]
+                  "alu_rate.hip", "prime.hip"]
 HOST_SOURCES = ["api.cpp", "plan.cpp", "batch.cpp", "tune.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]

@@ -16,6 +16,7 @@
 #include "kernels.hpp"
 #include "nega.hpp"
 #include "plan.hpp"
+#include "prime.hpp"
 #include "ss.hpp"
 
 static_assert(tft::kSplitDC == TFT_SPLIT_DC, "divide-and-conquer split code");
@@ -37,6 +38,12 @@ struct tft_plan {
     LeafProg *d_progs = nullptr;
     LeafStep *d_steps = nullptr;
     LeafOp *d_ops = nullptr;
+    // Z/pZ only: per-op twiddles (Montgomery theta^b; theta^-b for the inverse
+    // butterfly) and the twist-table width (every op's alog < zw)
+    std::vector<uint32_t> optw;
+    uint32_t zw = 0;
+    size_t bw = 0;
+    uint32_t *d_optw = nullptr;
     std::mutex mu;
 };
 
@@ -63,17 +70,28 @@ int check_ring(const tft_ring *r) {
         if (r->m < 3 || !(r->m & 1) || r->m >= (1ull << 62)) return TFT_E_RING;
         return TFT_OK;
     }
+    if (r->kind == TFT_RING_PRIME) {
+        if (r->N || r->K || r->reserved || r->m != zp::P) return TFT_E_RING;
+        return TFT_OK;
+    }
     return TFT_E_RING;
 }
 
-uint32_t ring_ord(const tft_ring *r) { return r->kind == TFT_RING_FERMAT ? 2u * r->N : 2u * r->K; }
+uint32_t ring_ord(const tft_ring *r) {
+    if (r->kind == TFT_RING_PRIME) return zp::ORD;
+    return r->kind == TFT_RING_FERMAT ? 2u * r->N : 2u * r->K;
+}
 
 // LDS bytes of one cell inside a leaf workgroup
 uint64_t cell_lds_bytes(const tft_ring *r) {
+    if (r->kind == TFT_RING_PRIME) return 4;
     return r->kind == TFT_RING_FERMAT ? fermat_lds_cell_bytes(r->N / 32) : 8ull * r->K;
 }
 
 uint32_t max_leaf_log2(const tft_ring *r) {
+    // Z/pZ: leaves of 2^10 words, so that a workgroup holds 32 adjacent columns
+    // (128-byte row segments) of a column pass
+    if (r->kind == TFT_RING_PRIME) return 10;
     uint64_t cap = lds_budget_bytes() / cell_lds_bytes(r);
     uint32_t lg = 0;
     while ((2ull << lg) <= cap) lg++;
@@ -133,12 +151,14 @@ void plan_blob(tft_plan *p) {
     p->bp = al(S.progs.size() * sizeof(LeafProg));
     p->bs = al(S.steps.size() * sizeof(LeafStep));
     p->bo = al(std::max<size_t>(1, S.ops.size()) * sizeof(LeafOp));
-    p->blob.assign(p->bj + p->bp + p->bs + p->bo, 0);
+    p->bw = p->optw.empty() ? 0 : al(p->optw.size() * sizeof(uint32_t));
+    p->blob.assign(p->bj + p->bp + p->bs + p->bo + p->bw, 0);
     char *c = p->blob.data();
     if (!S.jobs.empty()) memcpy(c, S.jobs.data(), S.jobs.size() * sizeof(Job));
     if (!S.progs.empty()) memcpy(c + p->bj, S.progs.data(), S.progs.size() * sizeof(LeafProg));
     if (!S.steps.empty()) memcpy(c + p->bj + p->bp, S.steps.data(), S.steps.size() * sizeof(LeafStep));
     if (!S.ops.empty()) memcpy(c + p->bj + p->bp + p->bs, S.ops.data(), S.ops.size() * sizeof(LeafOp));
+    if (p->bw) memcpy(c + p->bj + p->bp + p->bs + p->bo, p->optw.data(), p->optw.size() * sizeof(uint32_t));
 }
 
 // Descriptor pointers of a blob placed at device address d.
@@ -148,6 +168,7 @@ void plan_point(tft_plan *p, void *d) {
     p->d_progs = reinterpret_cast<LeafProg *>(c + p->bj);
     p->d_steps = reinterpret_cast<LeafStep *>(c + p->bj + p->bp);
     p->d_ops = reinterpret_cast<LeafOp *>(c + p->bj + p->bp + p->bs);
+    p->d_optw = p->bw ? reinterpret_cast<uint32_t *>(c + p->bj + p->bp + p->bs + p->bo) : nullptr;
 }
 
 int plan_upload(tft_plan *p) {
@@ -174,6 +195,29 @@ int plan_upload(tft_plan *p) {
     return TFT_OK;
 }
 
+// Z/pZ plans: each pass's jobs in order of (stride, first cell), so that a
+// workgroup's pack of jobs is adjacent columns (or rows); the per-op twiddle
+// table; the twist-table width.  Jobs of a pass are independent, their order
+// changes no output.
+void zp_prepare(tft_plan *p) {
+    Schedule &S = p->sched;
+    for (const PassDesc &pd : S.passes)
+        std::stable_sort(S.jobs.begin() + pd.job_begin, S.jobs.begin() + pd.job_begin + pd.job_count,
+                         [](const Job &a, const Job &b) {
+                             return a.stride != b.stride ? a.stride < b.stride : a.base < b.base;
+                         });
+    p->optw.resize(S.ops.size());
+    uint32_t amax = 0;
+    for (size_t i = 0; i < S.ops.size(); i++) {
+        const LeafOp &o = S.ops[i];
+        const uint32_t b = op_b(o);
+        amax = std::max(amax, op_alog(o));
+        const uint64_t e = (o.w0 & 15u) == OP_I2 ? (uint64_t)zp::ORD - b : b;
+        p->optw[i] = zp::theta_pow_m(e);
+    }
+    p->zw = amax + 1u;
+}
+
 tft_plan *plan_build(const tft_ring *ring, uint32_t dir, uint32_t l, uint64_t s, uint64_t z, uint64_t n, uint32_t f,
                      const tft_split *split) {
     tft_plan *p = new tft_plan();
@@ -191,6 +235,7 @@ tft_plan *plan_build(const tft_ring *ring, uint32_t dir, uint32_t l, uint64_t s,
     uint32_t top = 0;
     if (split && split->top_l1 && (split->top_l1 == kSplitDC || split->top_l1 < l)) top = split->top_l1;
     p->sched = build_schedule(dir, l, ring_ord(ring), p->s, z, n, p->f, leaf, top);
+    if (ring->kind == TFT_RING_PRIME) zp_prepare(p);
     const uint32_t seg = ring->kind == TFT_RING_FERMAT ? std::min<uint32_t>(ring->N / 32, 64) : 64;
     const uint32_t G = 64 / seg;
     for (const PassDesc &pd : p->sched.passes) {
@@ -260,7 +305,10 @@ int plan_launch(tft_plan *p, void *x, hipStream_t st, LaunchTimer *lt, bool tran
         const PassDesc &pd = p->sched.passes[i];
         hipError_t e = hipSuccess;
         if (lt && (e = lt->mark(st, true)) != hipSuccess) return dev_fail(e, "timer");
-        if (p->ring.kind == TFT_RING_FERMAT)
+        if (p->ring.kind == TFT_RING_PRIME)
+            e = launch_zp_leaf(pd.job_count, pd.max_len, p->d_jobs, pd.job_begin, p->d_progs, p->d_steps, p->d_ops,
+                               p->d_optw, static_cast<uint32_t *>(x), p->zw, st);
+        else if (p->ring.kind == TFT_RING_FERMAT)
             e = launch_fermat_leaf(p->ring.N / 32, p->nwaves[i], pd.job_count, pd.max_len, p->d_jobs, pd.job_begin,
                                    p->d_progs, p->d_steps, p->d_ops, static_cast<uint32_t *>(x), cap, ord_mask,
                                    pd.opmask, transposed, st);
@@ -349,6 +397,7 @@ int tft_ring_check(const tft_ring *ring) { return check_ring(ring); }
 
 uint64_t tft_elem_bytes(const tft_ring *ring) {
     if (check_ring(ring)) return 0;
+    if (ring->kind == TFT_RING_PRIME) return 4;
     return ring->kind == TFT_RING_FERMAT ? 4ull * (ring->N / 32 + 1) : 8ull * ring->K;
 }
 
@@ -433,8 +482,8 @@ int tft_plan_export(const tft_plan *plan, uint64_t *buf, uint64_t cap_words, uin
         *w++ = o.w0 & 15u;
         *w++ = (o.w0 >> 4) & 16383u;
         *w++ = (o.w0 >> 18) & 16383u;
-        *w++ = o.w1 >> 24;
-        *w++ = o.w1 & 0xFFFFFFu;
+        *w++ = op_alog(o);
+        *w++ = op_b(o);
     }
     return TFT_OK;
 }
@@ -486,6 +535,9 @@ int pointwise_mul(const tft_ring *ring, uint64_t n, const void *a, const void *b
     if (!a || !b || !c || n > cap || n > 0xFFFFFFFFull) return TFT_E_ARG;
     hipStream_t hs = static_cast<hipStream_t>(stream);
     const uint32_t ord = ring_ord(ring);
+    if (ring->kind == TFT_RING_PRIME)
+        return hip_status(launch_zp_pointwise(n, static_cast<const uint32_t *>(a), static_cast<const uint32_t *>(b),
+                                              static_cast<uint32_t *>(c), scale_log2, hs));
     if (ring->kind == TFT_RING_FERMAT) {
         const uint32_t e = (uint32_t)((ord - (scale_log2 % ord)) % ord);
         return hip_status(launch_fermat_pointwise(ring->N / 32, n, static_cast<const uint32_t *>(a),
@@ -742,6 +794,61 @@ int zmx_mul_nussbaumer(const uint64_t *g, uint64_t len_g, const uint64_t *h, uin
     st = plan_run(cached_plan(&ring, 1, sh.l, 0, sh.n, sh.n, 0, nullptr), A, hs);
     if (st) return st;
     return hip_status(launch_nega_unpack(sh.K, m, A, sh.n, out, len_g + len_h - 1, hs));
+}
+
+// ---------------------------------------------------------------------------
+// (Z/pZ)[x] by TFT / pointwise products / ITFT over Z/pZ (Sect. 2, Sect. 6)
+// ---------------------------------------------------------------------------
+
+static int zp_shape(uint64_t len_g, uint64_t len_h, uint32_t pad_rows, uint32_t *l, uint64_t *nt) {
+    if (len_g < 1 || len_h < 1 || pad_rows > 1) return TFT_E_ARG;
+    const uint64_t n = len_g + len_h - 1;
+    const uint32_t lg = std::max<uint32_t>(1, log2u(n));
+    if (lg > 24) return TFT_E_ARG;
+    uint64_t t = n;
+    if (pad_rows) {  // whole rows of the paper's split (Sect. 6): L2 = 2^(l - floor(l/2))
+        const uint64_t L2 = 1ull << (lg - lg / 2);
+        t = (n + L2 - 1) / L2 * L2;
+    }
+    *l = lg;
+    *nt = t;
+    return TFT_OK;
+}
+
+int zpx_mul_ntt_workspace(uint64_t len_g, uint64_t len_h, uint64_t *bytes) {
+    uint32_t l;
+    uint64_t nt;
+    if (!bytes) return TFT_E_ARG;
+    int st = zp_shape(len_g, len_h, 0, &l, &nt);
+    if (st) return st;
+    *bytes = 2ull * (1ull << l) * 4ull;
+    return TFT_OK;
+}
+
+int zpx_mul_ntt(const uint32_t *g, uint64_t len_g, const uint32_t *h, uint64_t len_h, uint32_t pad_rows,
+                uint32_t *out, void *ws, uint64_t ws_bytes, void *stream) {
+    if (!g || !h || !out) return TFT_E_ARG;
+    uint32_t l;
+    uint64_t nt;
+    int st = zp_shape(len_g, len_h, pad_rows, &l, &nt);
+    if (st) return st;
+    const uint64_t L = 1ull << l, n = len_g + len_h - 1;
+    if (!ws || ws_bytes < 2ull * L * 4ull) return TFT_E_WORKSPACE;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const tft_ring ring{TFT_RING_PRIME, 0, 0, 0, zp::P};
+    uint32_t *A = static_cast<uint32_t *>(ws), *B = A + L;
+    // cells beyond the operand lengths are never read (Sect. 3: they hold zeros)
+    hipError_t e = hipMemcpyAsync(A, g, len_g * 4ull, hipMemcpyDeviceToDevice, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(B, h, len_h * 4ull, hipMemcpyDeviceToDevice, hs);
+    if (e != hipSuccess) return dev_fail(e, "operand copy");
+    st = plan_run(cached_plan(&ring, 0, l, 0, len_g, nt, 0, nullptr), A, hs);
+    if (!st) st = plan_run(cached_plan(&ring, 0, l, 0, len_h, nt, 0, nullptr), B, hs);
+    if (st) return st;
+    e = launch_zp_pointwise(nt, A, B, A, l, hs);
+    if (e != hipSuccess) return dev_fail(e, "pointwise");
+    st = plan_run(cached_plan(&ring, 1, l, 0, nt, nt, 0, nullptr), A, hs);
+    if (st) return st;
+    return hip_status(hipMemcpyAsync(out, A, n * 4ull, hipMemcpyDeviceToDevice, hs), "output copy");
 }
 
 }  // extern "C"

@@ -27,8 +27,11 @@ enum BaseOp : uint32_t {
     OP_I0Z1 = 10,   // ITFT n=0 z=1:     x0 <- x0 / 2
 };
 
-// w0 = opcode | i0 << 4 | i1 << 18 ; w1 = b | alog << 24.
+// w0 = opcode | i0 << 4 | i1 << 18 ; w1 = b | alog << 28 (b < 2^28: ord(theta)
+// up to 2^27 for Z/pZ; alog, the depth inside a leaf, < 16).
 // The operation's twist exponent is (s * 2^alog + b) mod ord(theta), s being the job's.
+constexpr uint32_t kOpAlogShift = 28;
+constexpr uint32_t kOpBMask = (1u << kOpAlogShift) - 1u;
 struct LeafOp {
     uint32_t w0;
     uint32_t w1;
@@ -82,10 +85,10 @@ struct UnpackDesc {
     uint32_t pad;
 };
 
-inline uint32_t op_code(const LeafOp &o) { return o.w0 & 15u; }
-inline uint32_t op_i0(const LeafOp &o) { return (o.w0 >> 4) & 16383u; }
-inline uint32_t op_i1(const LeafOp &o) { return (o.w0 >> 18) & 16383u; }
-inline uint32_t op_b(const LeafOp &o) { return o.w1 & 0xFFFFFFu; }
-inline uint32_t op_alog(const LeafOp &o) { return o.w1 >> 24; }
+constexpr uint32_t op_code(const LeafOp &o) { return o.w0 & 15u; }
+constexpr uint32_t op_i0(const LeafOp &o) { return (o.w0 >> 4) & 16383u; }
+constexpr uint32_t op_i1(const LeafOp &o) { return (o.w0 >> 18) & 16383u; }
+constexpr uint32_t op_b(const LeafOp &o) { return o.w1 & kOpBMask; }
+constexpr uint32_t op_alog(const LeafOp &o) { return o.w1 >> kOpAlogShift; }
 
 }  // namespace tft

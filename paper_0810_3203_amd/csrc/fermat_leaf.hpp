@@ -170,7 +170,7 @@ __device__ __forceinline__ void leaf_body(const Job *__restrict__ jobs, const Le
                 const uint32_t code = o.w0 & 15u;
                 const uint32_t i0 = (o.w0 >> 4) & 16383u, i1 = (o.w0 >> 18) & 16383u;
                 const uint32_t e =
-                    (uint32_t)((((uint64_t)J.s << (o.w1 >> 24)) + (uint64_t)(o.w1 & 0xFFFFFFu)) & ord_mask);
+                    (uint32_t)((((uint64_t)J.s << op_alog(o)) + (uint64_t)op_b(o)) & ord_mask);
                 uint32_t *x0 = sm + i0 * F::ESZ, *x1 = sm + i1 * F::ESZ;
                 uint32_t *t0 = stop + i0, *t1 = stop + i1;
                 switch (code) {

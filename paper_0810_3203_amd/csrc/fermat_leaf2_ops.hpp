@@ -405,7 +405,7 @@ TFT_DINL void base_case(const Big<C> &ar, uint32_t *sm, const LeafOp &o, uint32_
                         uint32_t cofs = 0u) {
     constexpr uint32_t W = Big<C>::W;
     const uint32_t i01[2] = {((o.w0 >> 4) & 16383u) + cofs, ((o.w0 >> 18) & 16383u) + cofs};
-    const uint32_t ex = (uint32_t)((((uint64_t)s << (o.w1 >> 24)) + (uint64_t)(o.w1 & 0xFFFFFFu)) & ord_mask);
+    const uint32_t ex = (uint32_t)((((uint64_t)s << op_alog(o)) + (uint64_t)op_b(o)) & ord_mask);
     const uint32_t exs[3] = {ex, (0u - ex) & ord_mask, ord_mask};  // e, -e, 2N - 1 (2^(2N-1) = 1/2)
     for (uint32_t seq = base_case_steps(o.w0 & 15u); seq != 0u; seq >>= 8) {
         const uint32_t m = seq & 255u;

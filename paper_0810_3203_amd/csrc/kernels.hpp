@@ -57,6 +57,16 @@ hipError_t launch_fermat_unpack(uint32_t W, const UnpackDesc *descs, uint32_t nd
                                 uint64_t max_len, uint32_t max_olimbs, bool bundled, const uint32_t *x, uint64_t cap,
                                 bool transposed, hipStream_t st);
 
+// Leaf pass over R = Z/pZ (prime.hip): jobs packed per workgroup, optw the
+// per-op twiddle table (Montgomery theta^b, theta^-b for the inverse
+// butterfly), zw = entries of each job's twist table (every op's alog < zw).
+hipError_t launch_zp_leaf(uint32_t njobs, uint32_t max_len, const Job *jobs, uint32_t job_begin,
+                          const LeafProg *progs, const LeafStep *steps, const LeafOp *ops, const uint32_t *optw,
+                          uint32_t *x, uint32_t zw, hipStream_t st);
+// c_i = a_i b_i 2^-scale_log2 in Z/pZ for i < n.
+hipError_t launch_zp_pointwise(uint64_t n, const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t scale_log2,
+                               hipStream_t st);
+
 // Largest LDS bytes one workgroup may use.
 uint32_t lds_budget_bytes();
 

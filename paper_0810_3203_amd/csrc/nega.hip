@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(512) nega_leaf_kernel(const Job *__restrict__ 
                 const uint32_t code = o.w0 & 15u;
                 const uint32_t i0 = (o.w0 >> 4) & 16383u, i1 = (o.w0 >> 18) & 16383u;
                 const uint32_t e =
-                    (uint32_t)((((uint64_t)J.s << (o.w1 >> 24)) + (uint64_t)(o.w1 & 0xFFFFFFu)) & ord_mask);
+                    (uint32_t)((((uint64_t)J.s << op_alog(o)) + (uint64_t)op_b(o)) & ord_mask);
                 uint64_t *x0 = smq + (size_t)i0 * K, *x1 = smq + (size_t)i1 * K;
                 switch (code) {
                     case OP_T22: B.t22(x0, x1, e); break;

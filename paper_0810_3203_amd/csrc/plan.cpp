@@ -158,7 +158,7 @@ struct Builder {
             std::stable_sort(st.begin(), st.end(), [](const SymOp &a, const SymOp &b) { return a.code < b.code; });
             LeafStep ls{(uint32_t)S->ops.size(), (uint32_t)st.size()};
             for (const SymOp &o : st) {
-                S->ops.push_back({o.code | (o.i0 << 4) | (o.i1 << 18), (o.b & 0xFFFFFFu) | (o.alog << 24)});
+                S->ops.push_back({o.code | (o.i0 << 4) | (o.i1 << 18), (o.b & kOpBMask) | (o.alog << kOpAlogShift)});
                 opmask |= 1u << o.code;
             }
             S->steps.push_back(ls);

@@ -1,0 +1,198 @@
+"""GPU parity of the transforms, pointwise products and (Z/pZ)[x] products over
+R = Z/pZ, p = 15 2^27 + 1 (the small-coefficient case of Sect. 6), through the C
+ABI, against the oracle: eq. (1) written out (small lengths, every output), the
+C oracle's eq. (1) at sampled indices (large lengths), the ITFT by its
+definition (Sect. 2), and schoolbook products mod p.  Every comparison is exact.
+"""
+
+import random
+
+import numpy as np
+import pytest
+
+from oracle import tft_oracle as O
+from tests.gpu_util import note
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_0810_3203_amd as T  # noqa: E402
+
+RING = O.PrimeRing(T.PRIME_P)
+R = T.prime_ring()
+
+
+def _dev(vals, cap):
+    arr = np.zeros(cap, dtype=np.uint32)
+    arr[: len(vals)] = np.array(vals, dtype=np.uint64).astype(np.uint32)
+    return torch.from_numpy(arr.view(np.int32)).cuda()
+
+
+def _host(t, count):
+    return [int(v) for v in t.cpu().numpy().view(np.uint32)[:count]]
+
+
+def _inputs(rng, count):
+    out = []
+    for _ in range(count):
+        k = rng.randrange(8)
+        out.append(0 if k == 0 else (RING.p - 1 if k == 1 else (1 if k == 2 else rng.randrange(RING.p))))
+    return out
+
+
+def _tft(l, s, z, n, seed, top=0, leaf=0):
+    rng = random.Random(seed)
+    L = 1 << l
+    a = _inputs(rng, L)  # cells at and beyond z are never read
+    x = _dev(a, L)
+    note("prime tft l=%d s=%d z=%d n=%d split %d/%d" % (l, s, z, n, top, leaf))
+    if top or leaf:
+        T.Plan(R, 0, l, s, z, n, 0, top, leaf).execute(x)
+    else:
+        T.tft_forward(R, l, s, z, n, x)
+    torch.cuda.synchronize()
+    assert _host(x, n) == O.tft(RING, L, s, z, n, a[:z]), (l, s, z, n, top, leaf)
+
+
+def _itft(l, s, z, n, f, seed, top=0, leaf=0):
+    rng = random.Random(seed)
+    L = 1 << l
+    a = _inputs(rng, z)
+    inputs, expect = O.itft_case(RING, L, s, z, n, f, a)
+    x = _dev(list(inputs) + _inputs(rng, L - z), L)
+    note("prime itft l=%d s=%d z=%d n=%d f=%d split %d/%d" % (l, s, z, n, f, top, leaf))
+    if top or leaf:
+        T.Plan(R, 1, l, s, z, n, f, top, leaf).execute(x)
+    else:
+        T.itft_inverse(R, l, s, z, n, f, x)
+    torch.cuda.synchronize()
+    assert _host(x, n + f) == expect, (l, s, z, n, f, top, leaf)
+
+
+@pytest.mark.parametrize("l", [1, 2, 3, 5, 7])
+def test_prime_tft_small(l):
+    rng = random.Random(l)
+    L = 1 << l
+    for z, n in sorted({(L, L), (1, 1), (1, L), (L, 1), (rng.randint(1, L), rng.randint(1, L))}):
+        for s in (0, 1, 12345, (1 << 27) - 1):
+            _tft(l, s, z, n, seed=z * 31 + n + s)
+
+
+@pytest.mark.parametrize("l", [1, 2, 3, 5, 7])
+def test_prime_itft_small(l):
+    rng = random.Random(l + 100)
+    L = 1 << l
+    cases = {(L, L, 0), (1, 1, 0), (1, 0, 1), (L, L - 1, 1), (L, 0, 1)}
+    z = rng.randint(1, L)
+    cases.add((z, rng.randint(0, z - 1) if z > 1 else 0, 1))
+    for z, n, f in sorted(cases):
+        if not (1 <= n + f <= L):
+            continue
+        for s in (0, 3, 99999):
+            _itft(l, s, z, n, f, seed=z * 17 + n * 3 + f + s)
+
+
+def test_prime_every_split():
+    """Any top split, divide and conquer, and small leaves give the same outputs (Sect. 1)."""
+    for top in (1, 2, 3, 4, 5, T.SPLIT_DC):
+        for leaf in (1, 2, 3):
+            _tft(6, 77, 40, 61, seed=top + leaf, top=top, leaf=leaf)
+            _itft(6, 77, 61, 45, 1, seed=top * leaf, top=top, leaf=leaf)
+
+
+@pytest.mark.parametrize("l,z,n", [(12, 4096, 4096), (12, 3000, 4001), (16, 40000, 65536), (16, 65536, 33333),
+                                   (20, 600001, 999999), (22, 3000000, 4194304)])
+def test_prime_tft_large_sampled(coracle, l, z, n):
+    """Multi-pass TFTs at 2^12 .. 2^22 against eq. (1) at sampled indices:
+    the first and last outputs, every 2^(l/2)-th (row starts), and random ones."""
+    L = 1 << l
+    rng = np.random.default_rng(l + z)
+    a = rng.integers(0, RING.p, size=L, dtype=np.uint64).astype(np.uint32)
+    a[0], a[z - 1] = RING.p - 1, 0
+    s = 5 if l % 2 else 0
+    x = torch.from_numpy(a.view(np.int32).copy()).cuda()
+    note("prime tft large l=%d z=%d n=%d" % (l, z, n))
+    T.tft_forward(R, l, s, z, n, x)
+    torch.cuda.synchronize()
+    got = x.cpu().numpy().view(np.uint32)
+    pyr = random.Random(l)
+    step = 1 << (l - l // 2)
+    js = sorted({*range(min(n, 24)), *range(max(0, n - 24), n), *range(0, n, max(1, n // 64)),
+                 *(min(n - 1, k * step) for k in range(0, n // step + 1, max(1, n // step // 16))),
+                 *(pyr.randrange(n) for _ in range(96))})
+    want = coracle.prime_dft_sampled(RING, L, s, a[:z], js)
+    bad = [j for j, w in zip(js, want) if int(got[j]) != int(w)]
+    assert not bad, "outputs differ at %s" % bad[:8]
+
+
+@pytest.mark.parametrize("l,n,s", [(14, 16384, 0), (18, 200001, 7), (20, 1 << 20, 0), (21, 1500000, 3)])
+def test_prime_roundtrip_large(l, n, s):
+    """ITFT(L, zeta, n, n, 0) of TFT(L, zeta, n, n) returns L a_i for every i < n (Sect. 2)."""
+    L = 1 << l
+    rng = np.random.default_rng(l)
+    a = rng.integers(0, RING.p, size=L, dtype=np.uint64).astype(np.uint32)
+    x = torch.from_numpy(a.view(np.int32).copy()).cuda()
+    note("prime round trip l=%d n=%d s=%d" % (l, n, s))
+    T.tft_forward(R, l, s, n, n, x)
+    T.itft_inverse(R, l, s, n, n, 0, x)
+    torch.cuda.synchronize()
+    got = x.cpu().numpy().view(np.uint32)[:n].astype(np.uint64)
+    want = a[:n].astype(np.uint64) * np.uint64(L) % np.uint64(RING.p)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("scale", [0, 1, 17])
+def test_prime_pointwise(scale):
+    rng = random.Random(scale)
+    n = 5000
+    a, b = _inputs(rng, n), _inputs(rng, n)
+    da, db = _dev(a, n), _dev(b, n)
+    dc = torch.empty_like(da)
+    note("prime pointwise n=%d scale=%d" % (n, scale))
+    T.pointwise_mul(R, n, da, db, dc, n, scale)
+    torch.cuda.synchronize()
+    assert _host(dc, n) == O.pointwise(RING, a, b, scale)
+
+
+@pytest.mark.parametrize("lg,lh,pad", [(1, 1, 0), (1, 5, 0), (17, 9, 1), (100, 3, 0), (1000, 999, 1),
+                                        (4097, 3000, 0), (4097, 3000, 1)])
+def test_zpx_mul_small(lg, lh, pad):
+    rng = random.Random(lg * 7 + lh)
+    g, h = _inputs(rng, lg), _inputs(rng, lh)
+    g[0], h[-1] = RING.p - 1, RING.p - 1
+    out = torch.zeros(lg + lh - 1, dtype=torch.int32, device="cuda")
+    note("zpx_mul_ntt %d x %d pad=%d" % (lg, lh, pad))
+    T.zpx_mul_ntt(_dev(g, lg), _dev(h, lh), out, pad)
+    torch.cuda.synchronize()
+    assert _host(out, lg + lh - 1) == O.rx_mul_schoolbook(RING, g, h)
+
+
+@pytest.mark.parametrize("pad", [0, 1])
+def test_zpx_mul_large_sampled(coracle, pad):
+    """2^21 + 3 by 2^20 - 5 coefficients (transform length 2^22) against the
+    schoolbook sum at sampled indices, and a Schwartz-Zippel check of the whole
+    output: sum_k u_k r^k = g(r) h(r) mod p at two random r."""
+    rng = np.random.default_rng(5 + pad)
+    lg, lh = (1 << 21) + 3, (1 << 20) - 5
+    g = rng.integers(0, RING.p, size=lg, dtype=np.uint64)
+    h = rng.integers(0, RING.p, size=lh, dtype=np.uint64)
+    dg = torch.from_numpy(g.astype(np.uint32).view(np.int32)).cuda()
+    dh = torch.from_numpy(h.astype(np.uint32).view(np.int32)).cuda()
+    out = torch.zeros(lg + lh - 1, dtype=torch.int32, device="cuda")
+    note("zpx_mul_ntt large pad=%d" % pad)
+    T.zpx_mul_ntt(dg, dh, out, pad)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32).astype(np.uint64)
+    pyr = random.Random(pad)
+    n = lg + lh - 1
+    ks = sorted({0, 1, 2, n - 1, n - 2, lh - 1, lh, lg - 1, lg, *(pyr.randrange(n) for _ in range(60))})
+    want = coracle.zmx_coeffs(g, h, RING.p, ks)
+    assert [int(got[k]) for k in ks] == [int(w) for w in want]
+    for _ in range(2):
+        r = pyr.randrange(2, RING.p - 1)
+        lhs = coracle.fingerprint64(got, RING.p, r)
+        rhs = coracle.fingerprint64(g, RING.p, r) * coracle.fingerprint64(h, RING.p, r) % RING.p
+        assert lhs == rhs

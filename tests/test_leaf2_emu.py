@@ -62,7 +62,7 @@ def _emulate_plan(emu_exe, N, direction, l, s, z, n, f, leaf, cells):
     W = N // 32
     L = 1 << l
     e = T.Plan(T.fermat_ring(N), direction, l, s, z, n, f, 0, leaf).export()
-    ops = [(code | (i0 << 4) | (i1 << 18), (b & 0xFFFFFF) | (alog << 24)) for code, i0, i1, alog, b in e["ops"]]
+    ops = [(code | (i0 << 4) | (i1 << 18), (b & 0xFFFFFFF) | (alog << 28)) for code, i0, i1, alog, b in e["ops"]]
     jobs = []
     for jb, jc, _ in e["passes"]:
         jobs.extend(e["jobs"][jb:jb + jc])
