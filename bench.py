@@ -450,6 +450,66 @@ def other_products(T, torch, reps=5):
     return out
 
 
+def prime_leg(T, torch, lg=1 << 23, lh=1 << 23, reps=5):
+    """The small-coefficient case (Sect. 6): the product of two polynomials of
+    2^23 coefficients in (Z/pZ)[x], p = 15 2^27 + 1 (n = 2^24 - 1, L = 2^24).
+    The two TFTs and the ITFT are timed one by one as plans made beforehand
+    (descriptors already in device memory; HIP events, median of reps) and
+    reported as algorithmic GB/s: the cells Alg. 1 / Alg. 2's top-level passes
+    read and write, 4 bytes each.  tft_forward, which also copies the plan's
+    descriptors to the device on every call, is timed beside them.  The whole
+    product through zpx_mul_ntt, with and without Sect. 6's whole-row padding,
+    is timed the same way; its output must not change with padding."""
+    import numpy as np
+    ring = T.prime_ring()
+    n = lg + lh - 1
+    l = max(1, (n - 1).bit_length())
+    L = 1 << l
+    rng = np.random.default_rng(6)
+    g = torch.from_numpy(rng.integers(0, T.PRIME_P, size=lg, dtype=np.uint64).astype(np.uint32).view(np.int32)).cuda()
+    h = torch.from_numpy(rng.integers(0, T.PRIME_P, size=lh, dtype=np.uint64).astype(np.uint32).view(np.int32)).cuda()
+    A = torch.zeros(L, dtype=torch.int32, device="cuda")
+    wsf = torch.empty(T.transform_workspace(ring, 0, l, 0, lg, n), dtype=torch.uint8, device="cuda")
+    pf = T.Plan(ring, 0, l, 0, lg, n)
+    pi = T.Plan(ring, 1, l, 0, n, n, 0)
+
+    def timed(fn, prep=None):
+        if prep:
+            prep()
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            if prep:
+                prep()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[len(ts) // 2]
+
+    tft_ms = timed(lambda: pf.execute(A), prep=lambda: A[:lg].copy_(g))
+    itft_ms = timed(lambda: pi.execute(A))
+    one_call_ms = timed(lambda: T.tft_forward(ring, l, 0, lg, n, A, wsf), prep=lambda: A[:lg].copy_(g))
+    cells = 2 * alg_cells_tft(l, lg, n) + alg_cells_itft(l, n, n, 0)
+    total = 2 * tft_ms + itft_ms
+    gbs = cells * 4 / (total * 1e-3) / 1e9
+    out0 = torch.empty(n, dtype=torch.int32, device="cuda")
+    out1 = torch.empty(n, dtype=torch.int32, device="cuda")
+    ws = torch.empty(2 * L * 4, dtype=torch.uint8, device="cuda")
+    prod_ms = timed(lambda: T.zpx_mul_ntt(g, h, out0, 0, ws))
+    prod_pad_ms = timed(lambda: T.zpx_mul_ntt(g, h, out1, 1, ws))
+    exp = pf.export()
+    return {"workload": "(Z/pZ)[x] product, p = 15 2^27 + 1: %d x %d coefficients, L = 2^%d, n = %d" % (lg, lh, l, n),
+            "tft_passes": len(exp["passes"]), "tft_ms": round(tft_ms, 4), "itft_ms": round(itft_ms, 4),
+            "tft_forward_call_ms": round(one_call_ms, 4), "alg_cells": cells, "alg_bytes": cells * 4,
+            "transforms_gb_per_s": round(gbs, 2), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "product_ms": round(prod_ms, 4), "product_whole_rows_ms": round(prod_pad_ms, 4),
+            "whole_rows_same_output": bool(torch.equal(out0, out1))}
+
+
 def padded_leg(T, torch, dg, dh, out, l, n, N, reps=3):
     """The same product with n rounded up to whole rows of the paper split
     (Sect. 6 zero-padding: no partial last row in the ITFT), with the forward
@@ -559,6 +619,8 @@ def main():
                          "of Z[x] products with 8000-bit coefficients (one JSON line)")
     ap.add_argument("--large-only", action="store_true",
                     help="only the large product (for profiler runs): no probe, other products or batch")
+    ap.add_argument("--prime-only", action="store_true",
+                    help="instead of the benchmark: only the (Z/pZ)[x] small-coefficient leg (one JSON line)")
     ap.add_argument("--alu-probe", action="store_true",
                     help="instead of the benchmark: only the register-only issue-rate probe (one JSON line)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -581,6 +643,9 @@ def main():
         return
     if args.alu_probe:
         print(json.dumps(alu_probe(T)), flush=True)
+        return
+    if args.prime_only:
+        print(json.dumps(prime_leg(T, torch)), flush=True)
         return
     spec = wl.ZX_CASES[3]
     g, h = wl.zx_operands(3)
@@ -679,6 +744,8 @@ def main():
         line["other_products"] = _leg(lambda: other_products(T, torch))
         _progress("(Z/mZ)[x] product transforms")
         line["nega_case4_transforms"] = _leg(lambda: nega_case4_transforms(T, torch))
+        _progress("(Z/pZ)[x] product (small coefficients)")
+        line["prime_small_coefficients"] = _leg(lambda: prime_leg(T, torch))
     if not args.no_batch and not args.large_only:
         line["batch"] = _leg(lambda: batch_leg(T, torch))
     if not args.no_cpu_baseline and not args.large_only:

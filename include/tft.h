@@ -88,6 +88,10 @@ typedef struct {
  * leaf_log2  log2 of the largest sub-transform run inside one workgroup's LDS;
  *            0 = the largest that fits.  A larger value is accepted for planning
  *            (tft_plan_export) but tft_plan_execute then returns TFT_E_UNSUPPORTED.
+ *            Below the top level, sub-transforms above the leaf are split with
+ *            the columns one leaf (Fermat and negacyclic rings) or into the
+ *            fewest leaf passes, as evenly as they allow (Z/pZ, whose one-word
+ *            cells make small jobs all overhead).
  *            Every split gives identical outputs. */
 typedef struct {
     uint32_t top_l1;
@@ -119,7 +123,8 @@ int tft_transform_workspace(const tft_ring *ring, uint32_t direction, uint32_t l
                             uint32_t f, uint64_t *bytes);
 
 /* TFT(L, zeta, z, n) of Sect. 2 computed in place by Alg. 1 (Sect. 3).
- *   l       transform length L = 2^l, 1 <= l <= 24; L must divide ord(theta).
+ *   l       transform length L = 2^l, 1 <= l <= 24 (l <= 27 over Z/pZ, where
+ *           ord(theta) = 2^27); L must divide ord(theta).
  *   s       zeta = theta^s (any s; taken mod ord(theta)).
  *   z, n    1 <= z <= L, 1 <= n <= L.
  *   x       cell array of capacity L.  Cells [0, z) hold a_0..a_{z-1}; cells
@@ -279,7 +284,7 @@ int zpx_mul_ntt_workspace(uint64_t len_g, uint64_t len_h, uint64_t *bytes);
 /* Product u = g h in (Z/pZ)[x], p = TFT_PRIME_P, through TFT(g), TFT(h), n
  * pointwise products and the ITFT over R = Z/pZ (Sect. 2; the small-coefficient
  * case of Sect. 6), n = len_g + len_h - 1, transform length 2^l the smallest
- * power of two >= n, l <= 24 (else TFT_E_ARG).
+ * power of two >= n, l <= 27 (else TFT_E_ARG).
  *   g, h      len_g, len_h coefficients (uint32, each < p), device memory.
  *   pad_rows  0: transforms truncated at n; 1: n rounded up to whole rows of
  *             the paper's split (L2 = 2^(l - floor(l/2))), Sect. 6's zero-padding

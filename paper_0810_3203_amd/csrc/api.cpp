@@ -89,9 +89,9 @@ uint64_t cell_lds_bytes(const tft_ring *r) {
 }
 
 uint32_t max_leaf_log2(const tft_ring *r) {
-    // Z/pZ: leaves of 2^10 words, so that a workgroup holds 32 adjacent columns
-    // (128-byte row segments) of a column pass
-    if (r->kind == TFT_RING_PRIME) return 10;
+    // Z/pZ: leaves of 2^12 words (16 KB), so that with balanced splits a
+    // transform of up to 2^24 cells takes two passes
+    if (r->kind == TFT_RING_PRIME) return 12;
     uint64_t cap = lds_budget_bytes() / cell_lds_bytes(r);
     uint32_t lg = 0;
     while ((2ull << lg) <= cap) lg++;
@@ -128,7 +128,7 @@ int hip_status(hipError_t e, const char *where = "launch") { return e == hipSucc
 int check_transform_args(const tft_ring *ring, uint32_t dir, uint32_t l, uint64_t z, uint64_t n, uint32_t f) {
     int st = check_ring(ring);
     if (st) return st;
-    if (l < 1 || l > 24) return TFT_E_ARG;
+    if (l < 1 || l > (ring->kind == TFT_RING_PRIME ? zp::ORD_LOG2 : 24u)) return TFT_E_ARG;
     const uint64_t L = 1ull << l;
     if (ring_ord(ring) % L) return TFT_E_RING;
     if (dir == 0) {
@@ -216,6 +216,14 @@ void zp_prepare(tft_plan *p) {
         p->optw[i] = zp::theta_pow_m(e);
     }
     p->zw = amax + 1u;
+    // the kernel loads a step's ops while the previous step runs, taking them
+    // to follow that step's ops directly; a plan that breaks this is refused
+    // at launch (zw = 0)
+    for (const LeafProg &P : S.progs)
+        for (uint32_t st = 1; st < P.step_count; st++) {
+            const LeafStep &a = S.steps[P.step_begin + st - 1], &b = S.steps[P.step_begin + st];
+            if (b.op_begin != a.op_begin + a.op_count) p->zw = 0;
+        }
 }
 
 tft_plan *plan_build(const tft_ring *ring, uint32_t dir, uint32_t l, uint64_t s, uint64_t z, uint64_t n, uint32_t f,
@@ -230,12 +238,13 @@ tft_plan *plan_build(const tft_ring *ring, uint32_t dir, uint32_t l, uint64_t s,
     p->f = dir ? f : 0;
     // an explicit leaf size is honoured as given (a plan is host data); plans whose
     // leaves exceed the LDS budget are refused when executed
+    const bool prime = ring->kind == TFT_RING_PRIME;
     uint32_t leaf = max_leaf_log2(ring);
-    if (split && split->leaf_log2) leaf = std::min<uint32_t>(11, split->leaf_log2);
+    if (split && split->leaf_log2) leaf = std::min<uint32_t>(prime ? 12 : 11, split->leaf_log2);
     uint32_t top = 0;
     if (split && split->top_l1 && (split->top_l1 == kSplitDC || split->top_l1 < l)) top = split->top_l1;
-    p->sched = build_schedule(dir, l, ring_ord(ring), p->s, z, n, p->f, leaf, top);
-    if (ring->kind == TFT_RING_PRIME) zp_prepare(p);
+    p->sched = build_schedule(dir, l, ring_ord(ring), p->s, z, n, p->f, leaf, top, prime);
+    if (prime) zp_prepare(p);
     const uint32_t seg = ring->kind == TFT_RING_FERMAT ? std::min<uint32_t>(ring->N / 32, 64) : 64;
     const uint32_t G = 64 / seg;
     for (const PassDesc &pd : p->sched.passes) {
@@ -306,7 +315,7 @@ int plan_launch(tft_plan *p, void *x, hipStream_t st, LaunchTimer *lt, bool tran
         hipError_t e = hipSuccess;
         if (lt && (e = lt->mark(st, true)) != hipSuccess) return dev_fail(e, "timer");
         if (p->ring.kind == TFT_RING_PRIME)
-            e = launch_zp_leaf(pd.job_count, pd.max_len, p->d_jobs, pd.job_begin, p->d_progs, p->d_steps, p->d_ops,
+            e = launch_zp_leaf(pd.job_count, pd.max_len, pd.max_ops, p->d_jobs, pd.job_begin, p->d_progs, p->d_steps, p->d_ops,
                                p->d_optw, static_cast<uint32_t *>(x), p->zw, st);
         else if (p->ring.kind == TFT_RING_FERMAT)
             e = launch_fermat_leaf(p->ring.N / 32, p->nwaves[i], pd.job_count, pd.max_len, p->d_jobs, pd.job_begin,
@@ -804,7 +813,7 @@ static int zp_shape(uint64_t len_g, uint64_t len_h, uint32_t pad_rows, uint32_t 
     if (len_g < 1 || len_h < 1 || pad_rows > 1) return TFT_E_ARG;
     const uint64_t n = len_g + len_h - 1;
     const uint32_t lg = std::max<uint32_t>(1, log2u(n));
-    if (lg > 24) return TFT_E_ARG;
+    if (lg > zp::ORD_LOG2) return TFT_E_ARG;
     uint64_t t = n;
     if (pad_rows) {  // whole rows of the paper's split (Sect. 6): L2 = 2^(l - floor(l/2))
         const uint64_t L2 = 1ull << (lg - lg / 2);

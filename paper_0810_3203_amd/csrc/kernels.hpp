@@ -60,7 +60,7 @@ hipError_t launch_fermat_unpack(uint32_t W, const UnpackDesc *descs, uint32_t nd
 // Leaf pass over R = Z/pZ (prime.hip): jobs packed per workgroup, optw the
 // per-op twiddle table (Montgomery theta^b, theta^-b for the inverse
 // butterfly), zw = entries of each job's twist table (every op's alog < zw).
-hipError_t launch_zp_leaf(uint32_t njobs, uint32_t max_len, const Job *jobs, uint32_t job_begin,
+hipError_t launch_zp_leaf(uint32_t njobs, uint32_t max_len, uint32_t max_ops, const Job *jobs, uint32_t job_begin,
                           const LeafProg *progs, const LeafStep *steps, const LeafOp *ops, const uint32_t *optw,
                           uint32_t *x, uint32_t zw, hipStream_t st);
 // c_i = a_i b_i 2^-scale_log2 in Z/pZ for i < n.

@@ -7,15 +7,21 @@
 namespace tft {
 namespace {
 
-// l1 of a sub-transform of length 2^lg (Alg. 1 / Alg. 2 split 2^l1 x 2^(lg-l1)):
-// the top level takes the chosen split (0: the paper's, lg/2); below it, a
-// transform of at most two leaves' levels keeps its columns one whole leaf
-// (rows get the remainder), so passes are whole leaves but one; deeper ones
-// are halved.  Every split gives the same outputs.
-uint32_t sub_split_l1(uint32_t lg, bool top, uint32_t top_l1, uint32_t leaf_log2) {
+// l1 of a sub-transform of length 2^lg > leaf (Alg. 1 / Alg. 2 split
+// 2^l1 x 2^(lg-l1)): the top level takes the chosen split (0: the paper's,
+// lg/2).  Below it, the leaf-major rule keeps the columns of a transform of at
+// most two leaves' levels one whole leaf (rows get the remainder) and halves
+// deeper ones; the balanced rule takes the fewest passes k = ceil(lg / leaf)
+// and splits as evenly as they allow, so no pass is left with tiny jobs.
+// Every split gives the same outputs.
+uint32_t sub_split_l1(uint32_t lg, bool top, uint32_t top_l1, uint32_t leaf_log2, bool balanced) {
     if (top_l1 == kSplitDC) return 1;
     if (top && top_l1 && top_l1 < lg) return top_l1;
     if (top) return lg / 2;
+    if (balanced) {
+        const uint32_t k = (lg + leaf_log2 - 1) / leaf_log2;
+        return (lg + k - 1) / k;
+    }
     if (lg <= 2 * leaf_log2) return leaf_log2;
     return lg / 2;
 }
@@ -50,6 +56,7 @@ struct Builder {
     uint32_t ord;
     uint32_t leaf_log2;
     uint32_t top_l1;
+    bool balanced;
     Schedule *S;
     std::map<std::tuple<uint32_t, uint32_t, uint64_t, uint64_t, uint32_t>, uint32_t> cache;
     std::vector<std::vector<Job>> passes;
@@ -179,7 +186,7 @@ struct Builder {
         passes[p].push_back({base, stride, prog, (uint32_t)(s % ord), (uint32_t)nload, (uint32_t)nstore});
     }
 
-    uint32_t split_l1(uint32_t lg, bool top) const { return sub_split_l1(lg, top, top_l1, leaf_log2); }
+    uint32_t split_l1(uint32_t lg, bool top) const { return sub_split_l1(lg, top, top_l1, leaf_log2, balanced); }
 
     // Alg. 1 on the view (base, stride) of length 2^lg, starting at pass p;
     // returns the first pass after it.
@@ -244,9 +251,10 @@ struct Builder {
 // Builder::plan_itft with each phase's depth the largest over its sub-plans.
 struct PassCounter {
     uint32_t leaf_log2, top_l1;
+    bool balanced;
     std::map<std::tuple<uint32_t, uint64_t, uint64_t, uint32_t, bool>, uint32_t> memo;
 
-    uint32_t l1_of(uint32_t lg, bool top) const { return sub_split_l1(lg, top, top_l1, leaf_log2); }
+    uint32_t l1_of(uint32_t lg, bool top) const { return sub_split_l1(lg, top, top_l1, leaf_log2, balanced); }
     uint32_t tft(uint32_t lg, uint64_t z, uint64_t n, bool top) {
         if (lg <= leaf_log2) return 1;
         auto key = std::make_tuple(lg, z, n, 0u, top);
@@ -291,13 +299,13 @@ struct PassCounter {
 }  // namespace
 
 uint32_t schedule_pass_count(uint32_t direction, uint32_t l, uint64_t z, uint64_t n, uint32_t f, uint32_t leaf_log2,
-                             uint32_t top_l1) {
-    PassCounter pc{leaf_log2 < 1 ? 1 : leaf_log2, top_l1, {}};
+                             uint32_t top_l1, bool balanced) {
+    PassCounter pc{leaf_log2 < 1 ? 1 : leaf_log2, top_l1, balanced, {}};
     return direction == 0 ? pc.tft(l, z, n, true) : pc.itft(l, z, n, f, true);
 }
 
 Schedule build_schedule(uint32_t direction, uint32_t l, uint32_t ord, uint64_t s, uint64_t z, uint64_t n, uint32_t f,
-                        uint32_t leaf_log2, uint32_t top_l1) {
+                        uint32_t leaf_log2, uint32_t top_l1, bool balanced) {
     Schedule S;
     S.direction = direction;
     S.ord = ord;
@@ -307,6 +315,7 @@ Schedule build_schedule(uint32_t direction, uint32_t l, uint32_t ord, uint64_t s
     B.ord = ord;
     B.leaf_log2 = leaf_log2 < 1 ? 1 : leaf_log2;
     B.top_l1 = top_l1;
+    B.balanced = balanced;
     B.S = &S;
     if (direction == 0)
         B.plan_tft(0, 1, l, s % ord, z, n, 0, true);

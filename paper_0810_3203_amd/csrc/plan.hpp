@@ -48,15 +48,19 @@ struct Schedule {
 // ITFT(L, theta^s, z, n, f) (direction 1) on an array of L = 2^l cells.
 // ord = order of theta; leaf_log2 = largest leaf (>= 1); top_l1 = 0 for the
 // paper's split, kSplitDC for L1 = 2 at every level above the leaf (van der
-// Hoeven's divide-and-conquer order).  Arguments must already be valid.
+// Hoeven's divide-and-conquer order).  Below the top, sub-transforms larger
+// than a leaf are split leaf-major (columns one whole leaf where two leaves
+// cover them) or, with balanced, into the fewest passes as evenly as they
+// allow (for small cells, where a pass of tiny jobs would be all overhead).
+// Arguments must already be valid.
 Schedule build_schedule(uint32_t direction, uint32_t l, uint32_t ord, uint64_t s, uint64_t z, uint64_t n, uint32_t f,
-                        uint32_t leaf_log2, uint32_t top_l1);
+                        uint32_t leaf_log2, uint32_t top_l1, bool balanced = false);
 
 // Number of passes build_schedule gives for the same arguments, from the
 // recursion alone (no jobs are built): the column and row sub-plans of one
 // level that share a shape take the same passes, so only the distinct shapes
 // of each level are followed.
 uint32_t schedule_pass_count(uint32_t direction, uint32_t l, uint64_t z, uint64_t n, uint32_t f, uint32_t leaf_log2,
-                             uint32_t top_l1);
+                             uint32_t top_l1, bool balanced = false);
 
 }  // namespace tft

@@ -27,9 +27,35 @@ namespace tft {
 
 namespace {
 
-constexpr uint32_t kZpThreads = 256;
-constexpr uint32_t kZpLdsWords = 40960;  // 160 KB
-constexpr uint32_t kDescWords = 8;      // base lo, base hi, stride lo, stride hi, nload, nstore, prog, s
+constexpr uint32_t kZpThreads = 512;
+constexpr uint32_t kZpLdsWords = 40896;  // 160 KB, one compute unit's LDS, less the static words of __syncthreads_or
+constexpr uint32_t kZpPairWords = 20416;  // two workgroups on a compute unit
+constexpr uint32_t kZpCUs = 256;        // compute units of the part (MI355X)
+constexpr uint32_t kDescWords = 8;       // base lo, base hi, stride lo, stride hi, nload, nstore, prog, s
+
+// theta^e in Montgomery form for 0 <= e < 2^27 from three tables of 512
+// entries: e = e0 + 2^9 e1 + 2^18 e2 and v[k][j] = theta^(j 2^(9k)).  Built
+// by repeated multiplication at compile time.
+struct ThetaPowTab {
+    uint32_t v[3][512];
+};
+constexpr ThetaPowTab make_theta_pow_tab() {
+    ThetaPowTab t{};
+    for (int k = 0; k < 3; ++k) {
+        const uint32_t g = zp::theta_pow_m(1ull << (9 * k));
+        uint32_t x = zp::to_mont(1u);
+        for (int j = 0; j < 512; ++j) {
+            t.v[k][j] = x;
+            x = zp::mont(x, g);
+        }
+    }
+    return t;
+}
+__constant__ ThetaPowTab kThetaPow = make_theta_pow_tab();
+
+__device__ __forceinline__ uint32_t theta_pow_tab(uint32_t e) {
+    return zp::mont(zp::mont(kThetaPow.v[0][e & 511u], kThetaPow.v[1][(e >> 9) & 511u]), kThetaPow.v[2][e >> 18]);
+}
 
 __device__ __forceinline__ void zp_base_case(uint32_t *c, uint32_t code, uint32_t i0, uint32_t i1, uint32_t zm) {
     using namespace zp;
@@ -79,13 +105,68 @@ __device__ __forceinline__ void zp_base_case(uint32_t *c, uint32_t code, uint32_
     }
 }
 
-// One base case (op j of a step) of job p: its cells at c, its twist table at zt.
-__device__ __forceinline__ void zp_op(uint32_t *c, const uint32_t *zt, uint32_t zw, const LeafOp &o, uint32_t tw) {
+// Where the jobs of a pack keep their cells and twist tables in LDS.
+struct PackLds {
+    uint32_t *dat;       // job p's cells at p * pitch
+    uint32_t pitch;
+    const uint32_t *zt;  // job p's table at p * 2 zw: theta^(s 2^a), then theta^(-s 2^a)
+    uint32_t zw;
+    bool uni;            // every job of the pack has the same twist s (a row pass)
+};
+
+// One base case (cells i0, i1; twiddle theta^(s 2^alog) times tw, tw = theta^b
+// or theta^-b) on jobs p0 .. p1-1 of a pack.  With one twist for the whole
+// pack (UNI) the twiddle is formed once.
+template <uint32_t CODE, bool UNI>
+__device__ __forceinline__ void zp_jobs(const PackLds &L, uint32_t p0, uint32_t p1, uint32_t i0, uint32_t i1,
+                                        uint32_t alog, uint32_t tw) {
+    constexpr bool TW = CODE == OP_T22 || CODE == OP_T21 || CODE == OP_I2 || CODE == OP_I1F1Z2 || CODE == OP_I1F1Z1;
+    const uint32_t zoff = (CODE == OP_I2 ? L.zw : 0u) + alog;
+    const uint32_t z0 = TW && UNI ? zp::mont(L.zt[zoff], tw) : 0u;
+    for (uint32_t p = p0; p < p1; ++p) {
+        const uint32_t zm = !TW ? 0u : UNI ? z0 : zp::mont(L.zt[2u * L.zw * p + zoff], tw);
+        zp_base_case(L.dat + p * L.pitch, CODE, i0, i1, zm);
+    }
+}
+
+template <bool UNI>
+__device__ __forceinline__ void zp_jobs_code(uint32_t code, const PackLds &L, uint32_t p0, uint32_t p1, uint32_t i0,
+                                             uint32_t i1, uint32_t alog, uint32_t tw) {
+    switch (code) {
+        case OP_T22: zp_jobs<OP_T22, UNI>(L, p0, p1, i0, i1, alog, tw); break;
+        case OP_T21: zp_jobs<OP_T21, UNI>(L, p0, p1, i0, i1, alog, tw); break;
+        case OP_T12: zp_jobs<OP_T12, UNI>(L, p0, p1, i0, i1, alog, tw); break;
+        case OP_I2: zp_jobs<OP_I2, UNI>(L, p0, p1, i0, i1, alog, tw); break;
+        case OP_I1F1Z2: zp_jobs<OP_I1F1Z2, UNI>(L, p0, p1, i0, i1, alog, tw); break;
+        case OP_I1F1Z1: zp_jobs<OP_I1F1Z1, UNI>(L, p0, p1, i0, i1, alog, tw); break;
+        case OP_I1F0Z2: zp_jobs<OP_I1F0Z2, UNI>(L, p0, p1, i0, i1, alog, tw); break;
+        case OP_I1F0Z1: zp_jobs<OP_I1F0Z1, UNI>(L, p0, p1, i0, i1, alog, tw); break;
+        case OP_I0Z2: zp_jobs<OP_I0Z2, UNI>(L, p0, p1, i0, i1, alog, tw); break;
+        case OP_I0Z1: zp_jobs<OP_I0Z1, UNI>(L, p0, p1, i0, i1, alog, tw); break;
+        default: break;
+    }
+}
+
+// Op o of a step on jobs p0 .. p1-1.  A step's ops are grouped by opcode, so a
+// wave's lanes mostly share it: then the opcode is taken as a wave-uniform
+// value and the dispatch costs scalar branches only.
+template <bool UNI>
+__device__ __forceinline__ void zp_op_t(const LeafOp &o, uint32_t tw, const PackLds &L, uint32_t p0, uint32_t p1) {
     const uint32_t code = o.w0 & 15u;
     const uint32_t i0 = (o.w0 >> 4) & 16383u, i1 = (o.w0 >> 18) & 16383u;
     const uint32_t alog = op_alog(o);
-    const uint32_t zm = zp::mont(zt[(code == OP_I2 ? zw : 0u) + alog], tw);
-    zp_base_case(c, code, i0, i1, zm);
+    const uint32_t c0 = __builtin_amdgcn_readfirstlane(code);
+    if (__builtin_amdgcn_ballot_w64(code != c0) == 0)
+        zp_jobs_code<UNI>(c0, L, p0, p1, i0, i1, alog, tw);
+    else
+        zp_jobs_code<UNI>(code, L, p0, p1, i0, i1, alog, tw);
+}
+
+__device__ __forceinline__ void zp_op(const LeafOp &o, uint32_t tw, const PackLds &L, uint32_t p0, uint32_t p1) {
+    if (L.uni)
+        zp_op_t<true>(o, tw, L, p0, p1);
+    else
+        zp_op_t<false>(o, tw, L, p0, p1);
 }
 
 // floor(k / d) for k < 2^24 and 1 <= d < 2^24 (a float estimate, then one correction)
@@ -96,8 +177,15 @@ __device__ __forceinline__ uint32_t div_small(uint32_t k, uint32_t d, float rd) 
     return q;
 }
 
-// A workgroup runs jobs [first, first + count) of a pass, `pack` = 2^pack_log2
-// jobs of 2^slot_log2 cells at most; zw = twist entries per job (alog < zw).
+// A workgroup runs a pack of jobs [first, first + count) of a pass, at most
+// 2^pack_log2 jobs of at most 2^slot_log2 cells; zw = twist entries per job
+// (every op's alog < zw).  stage_cap > 0 (at least the widest step of the
+// pass) gives LDS room for that many ops, three words each: a pass of few
+// workgroups, one a compute unit, then copies its program's ops into LDS a
+// chunk of whole steps at a time instead of waiting on global memory at every
+// step.  Workgroups are numbered so that each XCD (the
+// hardware deals workgroup b to XCD b mod 8) takes a contiguous range of
+// packs: adjacent columns then share that XCD's L2.
 __global__ void __launch_bounds__(kZpThreads) zp_leaf_kernel(const Job *__restrict__ jobs,
                                                              const LeafProg *__restrict__ progs,
                                                              const LeafStep *__restrict__ steps,
@@ -105,17 +193,22 @@ __global__ void __launch_bounds__(kZpThreads) zp_leaf_kernel(const Job *__restri
                                                              const uint32_t *__restrict__ optw,
                                                              uint32_t *__restrict__ x, uint32_t job_begin,
                                                              uint32_t njobs, uint32_t pack_log2, uint32_t slot_log2,
-                                                             uint32_t zw) {
+                                                             uint32_t zw, uint32_t stage_cap) {
     extern __shared__ uint32_t sm[];
     const uint32_t tid = threadIdx.x;
+    const uint32_t G = gridDim.x, b = blockIdx.x, xcd = b & 7u, per = G >> 3, rem = G & 7u;
+    const uint32_t wg = (xcd < rem ? xcd * (per + 1u) : rem * (per + 1u) + (xcd - rem) * per) + (b >> 3);
     const uint32_t pack = 1u << pack_log2, slot = 1u << slot_log2, pitch = slot + 1u;
-    const uint32_t first = blockIdx.x * pack;
+    const uint32_t first = wg << pack_log2;
     const uint32_t count = njobs - first < pack ? njobs - first : pack;
     jobs += job_begin + first;
     uint32_t *dsc = sm;                          // kDescWords per job
-    uint32_t *ztab = dsc + kDescWords * pack;    // 2 zw per job: theta^(s 2^a), theta^(-s 2^a), Montgomery form
-    uint32_t *dat = ztab + 2u * zw * pack;       // job p's cells at p * pitch
+    uint32_t *ztab = dsc + kDescWords * pack;    // 2 zw per job
+    uint32_t *dat = ztab + 2u * zw * pack;
+    uint32_t *stage = dat + pack * pitch;        // stage_cap ops: w0, w1, twiddle
 
+    const uint32_t prog0 = jobs[0].prog, s0 = jobs[0].s;
+    int mixed = 0, twists = 0;
     for (uint32_t p = tid; p < count; p += kZpThreads) {
         const Job J = jobs[p];
         uint32_t *d = dsc + kDescWords * p;
@@ -127,14 +220,18 @@ __global__ void __launch_bounds__(kZpThreads) zp_leaf_kernel(const Job *__restri
         d[5] = J.nstore;
         d[6] = J.prog;
         d[7] = J.s;
+        mixed |= J.prog != prog0;
+        twists |= J.s != s0;
     }
-    for (uint32_t q = tid; q < count * zw; q += kZpThreads) {
-        const uint32_t p = q / zw, a = q - p * zw;
-        const uint64_t e = ((uint64_t)jobs[p].s << a) & (zp::ORD - 1u);
-        ztab[2u * zw * p + a] = zp::theta_pow_m(e);
-        ztab[2u * zw * p + zw + a] = zp::theta_pow_m(zp::ORD - e);
+    const uint32_t zs = 2u * zw;
+    const float rzs = 1.0f / (float)zs;
+    for (uint32_t q = tid; q < count * zs; q += kZpThreads) {
+        const uint32_t p = div_small(q, zs, rzs), a = q - p * zs;
+        const uint32_t e = (jobs[p].s << (a < zw ? a : a - zw)) & (zp::ORD - 1u);
+        ztab[q] = theta_pow_tab(a < zw ? e : (zp::ORD - e) & (zp::ORD - 1u));
     }
-    __syncthreads();
+    mixed = __syncthreads_or(mixed);
+    const PackLds L{dat, pitch, ztab, zw, __syncthreads_or(twists) == 0};
 
     // element e of the pack: (job, cell); rows read along the row, columns across jobs
     const bool rows = dsc[2] == 1u && dsc[3] == 0u;
@@ -153,40 +250,132 @@ __global__ void __launch_bounds__(kZpThreads) zp_leaf_kernel(const Job *__restri
         const uint64_t base = (uint64_t)d[1] << 32 | d[0], stride = (uint64_t)d[3] << 32 | d[2];
         return base + (uint64_t)r * stride;
     };
-    for (uint32_t e = tid; e < E; e += kZpThreads) {
-        uint32_t p, r;
-        elem(e, p, r);
-        if (p < count && r < dsc[kDescWords * p + 4]) dat[p * pitch + r] = x[gaddr(p, r)];
+    // eight loads in flight per thread before their LDS stores
+    for (uint32_t e0 = tid; e0 < E; e0 += 8u * kZpThreads) {
+        uint32_t v[8], at[8];
+#pragma unroll
+        for (uint32_t u = 0; u < 8u; ++u) {
+            const uint32_t e = e0 + u * kZpThreads;
+            uint32_t p = 0, r = 0;
+            if (e < E) elem(e, p, r);
+            at[u] = e < E && p < count && r < dsc[kDescWords * p + 4] ? p * pitch + r : ~0u;
+            if (at[u] != ~0u) v[u] = x[gaddr(p, r)];
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < 8u; ++u)
+            if (at[u] != ~0u) dat[at[u]] = v[u];
     }
     __syncthreads();
 
-    // the programs, step by step; all jobs of one program: items (job, op) with
-    // the op varying fastest; otherwise job after job
-    uint32_t same = 1u;
-    for (uint32_t p = 1; p < count; ++p) same &= dsc[kDescWords * p + 6] == dsc[6] ? 1u : 0u;
-    if (same) {
-        const LeafProg P = progs[dsc[6]];
+    const LeafProg P = progs[prog0];
+    if (!mixed && P.step_count && stage_cap) {
+        // ops staged in LDS: when a step's ops run past the staged window,
+        // the window moves to start at that step and takes as many ops as fit
+        const LeafStep SL = steps[P.step_begin + P.step_count - 1u];
+        const uint32_t op_end = SL.op_begin + SL.op_count;
+        uint32_t cb = 0, ce = 0;
         for (uint32_t st = 0; st < P.step_count; ++st) {
             const LeafStep LS = steps[P.step_begin + st];
-            const uint32_t oc = LS.op_count;
-            const float rd = 1.0f / (float)(oc ? oc : 1u);
-            const bool p2 = (oc & (oc - 1u)) == 0u;
-            uint32_t ol = 0;
-            while ((1u << ol) < oc) ++ol;
-            for (uint32_t k = tid; k < count * oc; k += kZpThreads) {
-                const uint32_t p = p2 ? k >> ol : div_small(k, oc, rd);
-                const uint32_t j = k - p * oc;
-                zp_op(dat + p * pitch, ztab + 2u * zw * p, zw, ops[LS.op_begin + j], optw[LS.op_begin + j]);
+            const uint32_t ob = LS.op_begin, oc = LS.op_count;
+            if (ob + oc > ce) {
+                cb = ob;
+                ce = op_end - cb < stage_cap ? op_end : cb + stage_cap;
+                for (uint32_t j0 = tid; j0 < ce - cb; j0 += 4u * kZpThreads) {
+                    LeafOp o[4];
+                    uint32_t t[4];
+#pragma unroll
+                    for (uint32_t u = 0; u < 4u; ++u) {
+                        const uint32_t j = j0 + u * kZpThreads;
+                        if (j < ce - cb) {
+                            o[u] = ops[cb + j];
+                            t[u] = optw[cb + j];
+                        }
+                    }
+#pragma unroll
+                    for (uint32_t u = 0; u < 4u; ++u) {
+                        const uint32_t j = j0 + u * kZpThreads;
+                        if (j < ce - cb) {
+                            stage[3u * j] = o[u].w0;
+                            stage[3u * j + 1u] = o[u].w1;
+                            stage[3u * j + 2u] = t[u];
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            const uint32_t *sg = stage + 3u * (ob - cb);
+            if (count == 1u || 2u * oc >= kZpThreads) {
+                for (uint32_t j = tid; j < oc; j += kZpThreads)
+                    zp_op(LeafOp{sg[3u * j], sg[3u * j + 1u]}, sg[3u * j + 2u], L, 0u, count);
+            } else {
+                const float rd = 1.0f / (float)oc;
+                for (uint32_t k = tid; k < count * oc; k += kZpThreads) {
+                    const uint32_t p = div_small(k, oc, rd), j = k - p * oc;
+                    zp_op(LeafOp{sg[3u * j], sg[3u * j + 1u]}, sg[3u * j + 2u], L, p, p + 1u);
+                }
             }
             __syncthreads();
         }
-    } else {
+    } else if (!mixed && P.step_count) {
+        // one program for the whole pack (a program of no steps, a transform
+        // whose base cases are all no-ops, leaves the cells as loaded).  Wide steps: a thread takes an op and
+        // runs it on every job of the pack (the op is read once); narrow
+        // steps: items (job, op) with the op varying fastest.  A program's
+        // steps keep their ops back to back, so the next step's ops (up to
+        // kPre a thread) are loaded while this step runs, bounded by the
+        // program's last op.
+        constexpr uint32_t kPre = 4;
+        const LeafStep S0 = steps[P.step_begin], SL = steps[P.step_begin + P.step_count - 1u];
+        const uint32_t op_end = SL.op_begin + SL.op_count;
+        LeafOp po[kPre];
+        uint32_t pt[kPre];
+        auto fetch = [&](uint32_t ob, LeafOp *o, uint32_t *t) {
+#pragma unroll
+            for (uint32_t i = 0; i < kPre; ++i) {
+                const uint32_t j = ob + tid + i * kZpThreads;
+                if (j < op_end) {
+                    o[i] = ops[j];
+                    t[i] = optw[j];
+                }
+            }
+        };
+        fetch(S0.op_begin, po, pt);
+        uint32_t ob = S0.op_begin, oc = S0.op_count;
+        for (uint32_t st = 0; st < P.step_count; ++st) {
+            const uint32_t nb = ob + oc;
+            const uint32_t noc = st + 1u < P.step_count ? steps[P.step_begin + st + 1u].op_count : 0u;
+            LeafOp no[kPre];
+            uint32_t nt[kPre];
+            fetch(nb, no, nt);
+            if (count == 1u || 2u * oc >= kZpThreads) {
+#pragma unroll
+                for (uint32_t i = 0; i < kPre; ++i)
+                    if (tid + i * kZpThreads < oc) zp_op(po[i], pt[i], L, 0u, count);
+                for (uint32_t j = tid + kPre * kZpThreads; j < oc; j += kZpThreads)
+                    zp_op(ops[ob + j], optw[ob + j], L, 0u, count);
+            } else {
+                const float rd = 1.0f / (float)oc;
+                for (uint32_t k = tid; k < count * oc; k += kZpThreads) {
+                    const uint32_t p = div_small(k, oc, rd), j = k - p * oc;
+                    zp_op(ops[ob + j], optw[ob + j], L, p, p + 1u);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (uint32_t i = 0; i < kPre; ++i) {
+                po[i] = no[i];
+                pt[i] = nt[i];
+            }
+            ob = nb;
+            oc = noc;
+        }
+    } else if (mixed) {
         for (uint32_t p = 0; p < count; ++p) {
-            const LeafProg P = progs[dsc[kDescWords * p + 6]];
-            for (uint32_t st = 0; st < P.step_count; ++st) {
-                const LeafStep LS = steps[P.step_begin + st];
+            const LeafProg Q = progs[dsc[kDescWords * p + 6]];
+            for (uint32_t st = 0; st < Q.step_count; ++st) {
+                const LeafStep LS = steps[Q.step_begin + st];
                 for (uint32_t j = tid; j < LS.op_count; j += kZpThreads)
-                    zp_op(dat + p * pitch, ztab + 2u * zw * p, zw, ops[LS.op_begin + j], optw[LS.op_begin + j]);
+                    zp_op(ops[LS.op_begin + j], optw[LS.op_begin + j], L, p, p + 1u);
                 __syncthreads();
             }
         }
@@ -211,14 +400,17 @@ __global__ void __launch_bounds__(256) zp_pointwise_kernel(const uint32_t *__res
 
 uint32_t zp_leaf_pack_log2(uint32_t njobs, uint32_t slot_log2, uint32_t zw) {
     const uint32_t per = kDescWords + 2u * zw + (1u << slot_log2) + 1u;
+    // two workgroups on a compute unit when a job fits half its LDS, else one
+    const uint32_t budget = per <= kZpPairWords ? kZpPairWords : kZpLdsWords;
     uint32_t pl = 0;
-    while ((2u << pl) * per <= kZpLdsWords && (2u << pl) <= 1024u) ++pl;
-    // keep at least two workgroups per compute unit when the pass has the jobs
-    while (pl > 0 && (njobs >> pl) < 512u) --pl;
+    while ((2u << pl) * per <= budget && (2u << pl) <= 256u) ++pl;
+    // about two packs per workgroup slot (256 compute units, two slots each)
+    // when the pass has the jobs
+    while (pl > 0 && (njobs >> pl) < 1024u) --pl;
     return pl;
 }
 
-hipError_t launch_zp_leaf(uint32_t njobs, uint32_t max_len, const Job *jobs, uint32_t job_begin,
+hipError_t launch_zp_leaf(uint32_t njobs, uint32_t max_len, uint32_t max_ops, const Job *jobs, uint32_t job_begin,
                           const LeafProg *progs, const LeafStep *steps, const LeafOp *ops, const uint32_t *optw,
                           uint32_t *x, uint32_t zw, hipStream_t st) {
     if (njobs == 0) return hipSuccess;
@@ -227,8 +419,17 @@ hipError_t launch_zp_leaf(uint32_t njobs, uint32_t max_len, const Job *jobs, uin
     if ((1u << sl) != max_len || zw == 0 || zw > 16) return hipErrorInvalidValue;
     const uint32_t pl = zp_leaf_pack_log2(njobs, sl, zw);
     const uint32_t pack = 1u << pl;
-    const size_t words = (size_t)pack * (kDescWords + 2u * zw + max_len + 1u);
+    size_t words = (size_t)pack * (kDescWords + 2u * zw + max_len + 1u);
     if (words > kZpLdsWords) return hipErrorInvalidValue;
+    const uint32_t grid = (njobs + pack - 1u) >> pl;
+    // no more workgroups than compute units: each has a compute unit's LDS,
+    // and the rest of it holds staged ops if the widest step fits
+    uint32_t stage_cap = 0;
+    if (grid <= kZpCUs) {
+        const uint32_t cap = (uint32_t)((kZpLdsWords - words) / 3u);
+        if (max_ops && cap >= max_ops) stage_cap = cap;
+    }
+    words += 3u * (size_t)stage_cap;
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&zp_leaf_kernel),
@@ -236,9 +437,8 @@ hipError_t launch_zp_leaf(uint32_t njobs, uint32_t max_len, const Job *jobs, uin
         if (e != hipSuccess) return e;
         attr = true;
     }
-    const uint32_t grid = (njobs + pack - 1u) >> pl;
     hipLaunchKernelGGL(zp_leaf_kernel, dim3(grid), dim3(kZpThreads), words * 4u, st, jobs, progs, steps, ops, optw, x,
-                       job_begin, njobs, pl, sl, zw);
+                       job_begin, njobs, pl, sl, zw, stage_cap);
     return hipGetLastError();
 }
 

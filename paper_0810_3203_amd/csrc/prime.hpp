@@ -34,20 +34,27 @@ constexpr uint32_t neg_inv_p() {
 constexpr uint32_t PINV = neg_inv_p();
 constexpr uint32_t R2 = (uint32_t)(((unsigned __int128)1 << 64) % P);  // R^2 mod P
 
+// Reductions by the unsigned minimum: for v < 2P, v - P wraps around to a
+// value above v exactly when v < P, so min(v, v - P) is v mod P.
+TFT_PHD constexpr uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
 TFT_PHD constexpr uint32_t mont(uint32_t a, uint32_t b) {
     const uint64_t t = (uint64_t)a * b;
     const uint32_t m = (uint32_t)t * PINV;
-    const uint64_t u = (t + (uint64_t)m * P) >> 32;  // < 2P
-    return u >= P ? (uint32_t)(u - P) : (uint32_t)u;
+    const uint32_t u = (uint32_t)((t + (uint64_t)m * P) >> 32);  // < 2P
+    return umin(u, u - P);
 }
 TFT_PHD constexpr uint32_t to_mont(uint32_t a) { return mont(a, R2); }
 TFT_PHD constexpr uint32_t from_mont(uint32_t a) { return mont(a, 1u); }
 TFT_PHD constexpr uint32_t add(uint32_t a, uint32_t b) {
     const uint32_t s = a + b;  // < 2P < 2^32
-    return s >= P ? s - P : s;
+    return umin(s, s - P);
 }
-TFT_PHD constexpr uint32_t sub(uint32_t a, uint32_t b) { return a >= b ? a - b : a + P - b; }
-TFT_PHD constexpr uint32_t half(uint32_t a) { return (a & 1u) ? (uint32_t)(((uint64_t)a + P) >> 1) : a >> 1; }
+// a - b wraps to at least 2^32 - P > P when a < b; adding P then brings it below P
+TFT_PHD constexpr uint32_t sub(uint32_t a, uint32_t b) {
+    const uint32_t d = a - b;
+    return umin(d, d + P);
+}
+TFT_PHD constexpr uint32_t half(uint32_t a) { return (a + ((a & 1u) ? P : 0u)) >> 1; }
 
 // b^e in Montgomery form, b given in Montgomery form
 TFT_PHD constexpr uint32_t pow_m(uint32_t bm, uint64_t e) {

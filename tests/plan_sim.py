@@ -15,7 +15,7 @@ OP_NONE, OP_T22, OP_T21, OP_T12, OP_I2, OP_I1F1Z2, OP_I1F1Z1, OP_I1F0Z2, OP_I1F0
 
 
 def _rand(ring, rng):
-    if ring.kind == "fermat":
+    if ring.kind in ("fermat", "prime"):
         return rng.randrange(ring.p)
     return tuple(rng.randrange(ring.m) for _ in range(ring.K))
 

@@ -144,6 +144,34 @@ def test_prime_roundtrip_large(l, n, s):
     assert np.array_equal(got, want)
 
 
+def test_prime_longest_transform(coracle):
+    """L = 2^27 = ord(theta), the longest transform over this ring (four
+    passes: 13 + 14 levels split again into leaves): the TFT against eq. (1)
+    at a few sampled indices, then ITFT(TFT(a)) = L a on every cell."""
+    l = 27
+    L = 1 << l
+    z, n = L - 12345, L - 999
+    rng = np.random.default_rng(27)
+    a = rng.integers(0, RING.p, size=L, dtype=np.uint32)
+    a[z:] = 0
+    x = torch.from_numpy(a.view(np.int32).copy()).cuda()
+    note("prime tft l=27 z=%d n=%d" % (z, n))
+    T.tft_forward(R, l, 3, z, n, x)
+    torch.cuda.synchronize()
+    got = x.cpu().numpy().view(np.uint32)
+    pyr = random.Random(27)
+    js = sorted({0, 1, n - 1, 1 << 13, 1 << 14, *(pyr.randrange(n) for _ in range(5))})
+    want = coracle.prime_dft_sampled(RING, L, 3, a[:z], js)
+    assert [int(got[j]) for j in js] == [int(w) for w in want]
+    note("prime round trip l=27")
+    x = torch.from_numpy(a.view(np.int32).copy()).cuda()
+    T.tft_forward(R, l, 0, n, n, x)
+    T.itft_inverse(R, l, 0, n, n, 0, x)
+    torch.cuda.synchronize()
+    back = x.cpu().numpy().view(np.uint32)[:n].astype(np.uint64)
+    assert np.array_equal(back, a[:n].astype(np.uint64) * np.uint64(L) % np.uint64(RING.p))
+
+
 @pytest.mark.parametrize("scale", [0, 1, 17])
 def test_prime_pointwise(scale):
     rng = random.Random(scale)

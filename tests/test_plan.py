@@ -28,10 +28,14 @@ def _rand(ring, rng):
         if k == 1:
             return 0
         return rng.randrange(ring.p)
+    if ring.kind == "prime":
+        return rng.randrange(ring.p)
     return tuple(rng.randrange(ring.m) for _ in range(ring.K))
 
 
 def _lib_ring(ring):
+    if ring.kind == "prime":
+        return T.prime_ring()
     return T.fermat_ring(ring.N) if ring.kind == "fermat" else T.nega_ring(ring.K, ring.m)
 
 
@@ -347,3 +351,39 @@ def test_sec6_partition():
     jb, jc, _ = d["passes"][1]
     stores = [j[5] for j in d["jobs"][jb:jb + jc]]
     assert stores.count(1 << (l - l1)) == full and stores.count(part) == 1 and len(stores) == full + 1
+
+
+PRIME = O.PrimeRing(T.PRIME_P)  # ord 2^27
+
+
+@pytest.mark.parametrize("leaf_log2", [1, 2, 3])
+def test_prime_balanced_schedules(leaf_log2):
+    """Z/pZ plans split sub-transforms above the leaf into the fewest passes,
+    as evenly as they allow; with small leaves that rule runs several levels
+    deep, and the schedules must still give eq. (1) and the ITFT's definition."""
+    rng = random.Random(leaf_log2 + 40)
+    for l in (5, 7, 9):
+        L = 1 << l
+        for z, n in {(L, L), (1, L), (rng.randint(1, L), rng.randint(1, L))}:
+            _check_tft(PRIME, l, rng.randrange(1 << 27), z, n, 0, leaf_log2, seed=z + n)
+        z = rng.randint(2, L)
+        n = rng.randint(0, z - 1)
+        _check_itft(PRIME, l, rng.randrange(1 << 27), z, n, 1, 0, leaf_log2, seed=z * 3 + n)
+        _check_itft(PRIME, l, 5, L, L, 0, 0, leaf_log2, seed=l)
+
+
+def test_prime_default_plan_shapes():
+    """Default Z/pZ plans: leaves of 2^12 words and balanced sub-splits, so a
+    transform of 2^24 takes two passes of 4096 jobs of 4096 cells (the paper's
+    split at the top), and 2^27 = 13 + 14 levels takes four passes with no job
+    below 2^6 cells."""
+    ring = T.prime_ring()
+    e = T.Plan(ring, 0, 24, 0, 1 << 23, (1 << 24) - 1).export()
+    assert e["leaf_log2"] == 12
+    assert [(c, m) for _, c, m in e["passes"]] == [(4096, 4096), (4096, 4096)]
+    assert {e["progs"][j[2]][2] for j in e["jobs"]} == {4096}
+    e = T.Plan(ring, 1, 24, 0, (1 << 24) - 1, (1 << 24) - 1, 0).export()
+    assert [c for _, c, _ in e["passes"]] == [4095, 1, 1, 4095]
+    e = T.Plan(ring, 0, 27, 0, 1 << 27, 1 << 27).export()
+    assert len(e["passes"]) == 4
+    assert min(e["progs"][j[2]][2] for j in e["jobs"]) >= 1 << 6
