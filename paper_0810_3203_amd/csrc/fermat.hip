@@ -6,6 +6,7 @@
 #include "desc.hpp"
 #include "fermat_dev.hpp"
 #include "fermat_leaf.hpp"
+#include "fermat_nested.hpp"
 #include "kernels.hpp"
 
 namespace tft {
@@ -63,6 +64,66 @@ constexpr int pw_cols(int W) { return W / (int)pw_threads(W) > 0 ? W / (int)pw_t
 // LDS words of a pointwise workgroup: A2 (2W), B (W), six column-word arrays (6W)
 constexpr uint32_t pw_lds_words(int W) { return 9u * (uint32_t)W; }
 
+// Last phase of a product: with the four limb arrays of LDS filled (A[j] and
+// Bv[j] the low words of the positive and negative sums landing on limb j,
+// P0[j] and N0[j] their high words, landing on limb j + 1), one wave adds
+// them with the chunk chains, takes the residue mod 2^N+1 and multiplies by
+// 2^scale_e; special = a or b is 2^N, with A and Bv then holding a and b.
+// The result is staged at the start of LDS (W + 1 words) before its store.
+// Called by a whole workgroup.
+template <int S, int C, bool TR>
+__device__ __forceinline__ void pointwise_finish(bool special, uint32_t ta, uint32_t tb, const uint32_t *A,
+                                                 const uint32_t *Bv, const uint32_t *P0, const uint32_t *N0,
+                                                 uint32_t *c, uint32_t *tc, uint32_t scale_e) {
+    using F = FChunk<S, C>;
+    constexpr int W = F::W;
+    extern __shared__ uint32_t sm[];
+    uint32_t *Y = sm;
+    uint32_t &topY = Y[F::ESZ];
+    const uint32_t tid = threadIdx.x, nthr = blockDim.x;
+    if (tid < 64) {
+        const FermatOps<F> Bo;
+        if (Bo.lane < (uint32_t)S) {  // segment 0 only
+            uint32_t s3[C];
+            uint32_t top;
+            if (!special) {
+                uint32_t pl[C], hp[C], nl[C], hn[C], s1[C], s2[C];
+#pragma unroll
+                for (int j = 0; j < C; ++j) {
+                    const uint32_t k = Bo.l * C + j;
+                    pl[j] = A[k];
+                    nl[j] = Bv[k];
+                    hp[j] = k ? P0[k - 1] : N0[W - 1];
+                    hn[j] = k ? N0[k - 1] : P0[W - 1];
+                }
+                const uint32_t c1 = Bo.add(s1, pl, hp);
+                const uint32_t b2 = Bo.sub(s2, s1, nl);
+                const uint32_t b3 = Bo.sub(s3, s2, hn);
+                top = Bo.canon(s3, (int)c1 - (int)b2 - (int)b3, 0, 0u);
+            } else if (ta && tb) {
+                // (-1)(-1) = 1
+#pragma unroll
+                for (int j = 0; j < C; ++j) s3[j] = 0u;
+                top = Bo.canon(s3, -1, 0, 0u);
+            } else {
+                // (-1) v = 2^N + 1 - v = ~v + 2
+                const uint32_t *v = ta ? Bv : A;
+#pragma unroll
+                for (int j = 0; j < C; ++j) s3[j] = ~v[Bo.l * C + j];
+                top = Bo.canon(s3, -2, 0, 0u);
+            }
+            Bo.st(Y, s3);
+            if (scale_e)
+                Bo.twist_store(Y, &topY, scale_e, (int)top);
+            else if (Bo.l == 0u)
+                topY = top;
+        }
+    }
+    __syncthreads();
+    for (uint32_t q = tid; q < (uint32_t)W; q += nthr) c[q] = Y[TR ? q : F::addr(q)];
+    if (tid == 0) *tc = topY;
+}
+
 // c = a b 2^scale_e for one product; a, b, c are W-limb cells (c may alias a or b),
 // ta, tb their top words, tc where c's top goes.  Called by a whole workgroup.
 template <int S, int C, bool TR>
@@ -74,8 +135,6 @@ __device__ __forceinline__ void pointwise_body(const uint32_t *a, uint32_t ta, c
     extern __shared__ uint32_t sm[];
     uint32_t *A = sm, *Bv = A + 2 * W;
     uint32_t *P0 = Bv + W, *P1 = P0 + W, *P2 = P1 + W, *N0 = P2 + W, *N1 = N0 + W, *N2 = N1 + W;
-    uint32_t *Y = sm;  // F::ESZ dwords (LDS layout of one element) plus its top: reuses A2 at the end
-    uint32_t &topY = Y[F::ESZ];
     const uint32_t tid = threadIdx.x, nthr = blockDim.x;
 
     for (uint32_t q = tid; q < (uint32_t)W; q += nthr) {
@@ -224,47 +283,212 @@ __device__ __forceinline__ void pointwise_body(const uint32_t *a, uint32_t ta, c
         __syncthreads();
     }
 
-    if (tid < 64) {
-        const FermatOps<F> Bo;
-        if (Bo.lane < (uint32_t)S) {  // segment 0 only
-            uint32_t s3[C];
-            uint32_t top;
-            if (!special) {
-                uint32_t pl[C], hp[C], nl[C], hn[C], s1[C], s2[C];
+    pointwise_finish<S, C, TR>(special, ta, tb, A, Bv, P0, N0, c, tc, scale_e);
+}
+
+// c = a b 2^scale_e for one product through one more Schoenhage-Strassen
+// level (fermat_nested.hpp), for W with a nest::Cfg; a and b not 2^N.
+// kNestThreads threads: the transforms give every lane a digit of a
+// butterfly; the inner products give each wave a group of columns of all K
+// products (a lane a product); carries are resolved a lane a cell.
+constexpr uint32_t kNestThreads = 256;
+
+// forward transform of the digit cells D (cell pitch WI + 1 int64): item =
+// (butterfly, digit); every item reads before any writes
+template <class NS>
+__device__ __forceinline__ void nested_forward(int64_t *D, uint32_t tid) {
+    constexpr int K = NS::K, WI = NS::WI, CP = WI + 1;
+    constexpr uint32_t T = kNestThreads, HW = (uint32_t)(K / 2 * WI), FI = (HW + T - 1u) / T;
+    for (int hs = K / 2; hs >= 1; hs >>= 1) {
+        int64_t sv[FI], ev[FI];
+        uint32_t xi[FI], yi[FI];
 #pragma unroll
-                for (int j = 0; j < C; ++j) {
-                    const uint32_t k = Bo.l * C + j;
-                    pl[j] = A[k];
-                    nl[j] = Bv[k];
-                    hp[j] = k ? P0[k - 1] : N0[W - 1];
-                    hn[j] = k ? N0[k - 1] : P0[W - 1];
+        for (uint32_t k = 0; k < FI; ++k) {
+            const uint32_t e = tid + k * T;
+            xi[k] = ~0u;
+            if (e < HW) {
+                const uint32_t t = e / WI, d = e - t * WI;
+                const uint32_t off = t % (uint32_t)hs, o = (t / (uint32_t)hs) * 2u * hs + off;
+                const int64_t x = D[o * CP + d], y = D[(o + hs) * CP + d];
+                uint32_t dd = d + (uint32_t)NS::twiddle_limbs((int)off, hs);
+                int64_t dv = x - y;
+                if (dd >= (uint32_t)WI) {  // past 2^N' = -1
+                    dd -= WI;
+                    dv = -dv;
                 }
-                const uint32_t c1 = Bo.add(s1, pl, hp);
-                const uint32_t b2 = Bo.sub(s2, s1, nl);
-                const uint32_t b3 = Bo.sub(s3, s2, hn);
-                top = Bo.canon(s3, (int)c1 - (int)b2 - (int)b3, 0, 0u);
-            } else if (ta && tb) {
-                // (-1)(-1) = 1
-#pragma unroll
-                for (int j = 0; j < C; ++j) s3[j] = 0u;
-                top = Bo.canon(s3, -1, 0, 0u);
-            } else {
-                // (-1) v = 2^N + 1 - v = ~v + 2
-                const uint32_t *v = ta ? Bv : A;
-#pragma unroll
-                for (int j = 0; j < C; ++j) s3[j] = ~v[Bo.l * C + j];
-                top = Bo.canon(s3, -2, 0, 0u);
+                sv[k] = x + y;
+                ev[k] = dv;
+                xi[k] = o * CP + d;
+                yi[k] = (o + hs) * CP + dd;
             }
-            Bo.st(Y, s3);
-            if (scale_e)
-                Bo.twist_store(Y, &topY, scale_e, (int)top);
-            else if (Bo.l == 0u)
-                topY = top;
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t k = 0; k < FI; ++k)
+            if (xi[k] != ~0u) {
+                D[xi[k]] = sv[k];
+                D[yi[k]] = ev[k];
+            }
+        __syncthreads();
+    }
+}
+
+template <int S, int C, bool TR>
+__device__ __forceinline__ void nested_body(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t *tc,
+                                            uint32_t scale_e) {
+    using F = FChunk<S, C>;
+    constexpr int W = F::W;
+    using NS = nest::Nest<W>;
+    constexpr int K = NS::K, WI = NS::WI, WP = NS::WP, NC = NS::NC, G = NS::G, CP = WI + 1, DP = NS::DP;
+    constexpr uint32_t T = kNestThreads, KW = (uint32_t)(K * WI), HW = (uint32_t)(K / 2 * WI);
+    static_assert(G * 64 == (int)T, "a wave per column group");
+    extern __shared__ uint32_t sm[];
+    int64_t *D = reinterpret_cast<int64_t *>(sm + NS::D);
+    uint32_t *LA = sm + NS::LA, *CWS = sm + NS::CW;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+
+    // a: split, transform, normalise into LA.  The split takes lane = cell
+    // and wave = a range of piece limbs: in the transposed layout limb k of
+    // the K pieces is one contiguous row, so each load is a whole row.
+    constexpr int KPW = NS::PL / G, DPW = (WI + G - 1) / G;
+    static_assert(KPW * G == NS::PL, "piece limbs split evenly over the waves");
+    auto split = [&](const uint32_t *x) {
+        auto limb = [&](int q) { return x[TR ? F::addr((uint32_t)q) : (uint32_t)q]; };
+        int64_t *cell = D + lane * CP;
+        const int d0 = (int)wave * DPW, d1 = d0 + DPW < WI ? d0 + DPW : WI;
+        NS::split_zero((int)lane, d0, d1, cell);
+        NS::split_part(limb, (int)lane, (int)wave * KPW, ((int)wave + 1) * KPW, cell);
+    };
+    split(a);
+    __syncthreads();
+    nested_forward<NS>(D, tid);
+    if (wave == 0u) NS::norm_digits(D + lane * CP, LA + lane * WP);
+    __syncthreads();
+    // b: the same, normalised in place in the digit region
+    split(b);
+    __syncthreads();
+    nested_forward<NS>(D, tid);
+    if (wave == 0u) NS::norm_digits(D + lane * CP, sm + NS::D + lane * DP);
+    __syncthreads();
+    // inner products: lane = position, wave = column group
+    uint32_t *Ai = LA + lane * WP;
+    const uint32_t *Bi = sm + NS::D + lane * DP;
+    const bool sp = NS::geth(Ai) != 0 || NS::geth(Bi) != 0;
+    uint32_t out[NC];
+    const int64_t cw = NS::columns(Ai, Bi, (int)wave * NC, out,
+                                   [](uint64_t (&acc)[NC], uint32_t (&cy)[NC], const uint32_t (&aw)[NC], uint32_t bj) {
+                                       static_for<0, NC / 4>(
+                                           [&](auto qc) { mac4<4 * decltype(qc)::value, NC>(acc, cy, aw, bj); });
+                                   });
+    __syncthreads();  // every wave has read its A columns
+    if (!sp) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) Ai[(int)wave * NC + k] = out[k];
+    }
+    CWS[2u * (wave * 64u + lane)] = (uint32_t)cw;
+    CWS[2u * (wave * 64u + lane) + 1u] = (uint32_t)((uint64_t)cw >> 32);
+    __syncthreads();
+    if (wave == 0u) {
+        if (sp) {
+            NS::special_product(Ai, Bi, Ai);
+        } else {
+            int64_t cws[G];
+#pragma unroll
+            for (int w = 0; w < G; ++w)
+                cws[w] = (int64_t)((uint64_t)CWS[2u * (w * 64u + lane) + 1u] << 32 | CWS[2u * (w * 64u + lane)]);
+            NS::settle_columns(Ai, cws);
         }
     }
     __syncthreads();
-    for (uint32_t q = tid; q < (uint32_t)W; q += nthr) c[q] = Y[TR ? q : F::addr(q)];
-    if (tid == 0) *tc = topY;
+    // products as digit cells (value L + h 2^N' = L - h)
+    for (uint32_t e = tid; e < KW; e += T) {
+        const uint32_t i = e / WI, d = e - i * WI;
+        int64_t v = LA[i * WP + d];
+        if (d == 0u) v -= NS::geth(LA + i * WP);
+        D[i * CP + d] = v;
+    }
+    __syncthreads();
+    // inverse transform: item = (butterfly, digit); t = y w^-off has digit d
+    // from y's digit d + q (negated past 2^N')
+    constexpr uint32_t II = (HW + T - 1u) / T;
+    for (int hs = 1; hs <= K / 2; hs <<= 1) {
+        int64_t xv[II], yv[II];
+        uint32_t xi[II], yi[II];
+#pragma unroll
+        for (uint32_t k = 0; k < II; ++k) {
+            const uint32_t e = tid + k * T;
+            xi[k] = ~0u;
+            if (e < HW) {
+                const uint32_t t = e / WI, d = e - t * WI;
+                const uint32_t off = t % (uint32_t)hs, o = (t / (uint32_t)hs) * 2u * hs + off;
+                const int64_t x = D[o * CP + d];
+                const uint32_t dq = d + (uint32_t)NS::twiddle_limbs((int)off, hs);
+                const int64_t y = dq < (uint32_t)WI ? D[(o + hs) * CP + dq] : -D[(o + hs) * CP + dq - WI];
+                xv[k] = x + y;
+                yv[k] = x - y;
+                xi[k] = o * CP + d;
+                yi[k] = (o + hs) * CP + d;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t k = 0; k < II; ++k)
+            if (xi[k] != ~0u) {
+                D[xi[k]] = xv[k];
+                D[yi[k]] = yv[k];
+            }
+        __syncthreads();
+    }
+    if (wave == 0u) NS::norm_digits(D + lane * CP, Ai);
+    __syncthreads();
+    // untwist and 1/K into the digit cells, then the signed coefficients
+    for (uint32_t e = tid; e < KW; e += T) {
+        const uint32_t i = e / WI, d = e - i * WI;
+        D[i * CP + d] = NS::untwist_digit(LA + i * WP, (int)i, (int)d);
+    }
+    __syncthreads();
+    if (wave == 0u) {
+        NS::norm_digits(D + lane * CP, Ai);
+        NS::magnitude(Ai, Ai);
+    }
+    __syncthreads();
+    // per-limb positive / negative sums in the last phase's arrays
+    for (uint32_t j = tid; j < (uint32_t)W; j += T) {
+        uint64_t pos, neg;
+        NS::gather(LA, (int)j, pos, neg);
+        sm[NS::PA + j] = (uint32_t)pos;
+        sm[NS::PB + j] = (uint32_t)neg;
+        sm[NS::P0 + j] = (uint32_t)(pos >> 32);
+        sm[NS::N0 + j] = (uint32_t)(neg >> 32);
+    }
+    __syncthreads();
+    pointwise_finish<S, C, TR>(false, 0u, 0u, sm + NS::PA, sm + NS::PB, sm + NS::P0, sm + NS::N0, c, tc, scale_e);
+}
+
+template <int S, int C, bool TR>
+__global__ void __launch_bounds__(kNestThreads, 2) fermat_pointwise_nested_kernel(const uint32_t *__restrict__ a,
+                                                                      const uint32_t *__restrict__ b, uint32_t *c,
+                                                                      uint64_t cap, uint32_t scale_e, uint32_t base) {
+    constexpr int W = S * C;
+    const uint64_t i = (uint64_t)base + blockIdx.x;
+    const uint32_t ta = a[cap * W + i], tb = b[cap * W + i];
+    if ((ta | tb) != 0u)
+        pointwise_body<S, C, TR>(a + i * W, ta, b + i * W, tb, c + i * W, c + cap * W + i, scale_e);
+    else
+        nested_body<S, C, TR>(a + i * W, b + i * W, c + i * W, c + cap * W + i, scale_e);
+}
+
+template <int S, int C, bool TR>
+__global__ void __launch_bounds__(kNestThreads, 2) fermat_pointwise_nested_items_kernel(uint32_t *x, uint64_t cap,
+                                                                            const uint4 *__restrict__ items) {
+    constexpr int W = S * C;
+    const uint4 it = items[blockIdx.x];
+    uint32_t *ca = x + (uint64_t)it.x * W, *cb = x + (uint64_t)it.y * W;
+    const uint32_t ta = x[cap * W + it.x], tb = x[cap * W + it.y];
+    if ((ta | tb) != 0u)
+        pointwise_body<S, C, TR>(ca, ta, cb, tb, ca, x + cap * W + it.x, it.z);
+    else
+        nested_body<S, C, TR>(ca, cb, ca, x + cap * W + it.x, it.z);
 }
 
 template <int S, int C, bool TR>
@@ -384,20 +608,57 @@ hipError_t pointwise_attr(KernelT *kern, size_t lds, bool &done) {
     return e;
 }
 
+// W with a nest::Cfg take the nested product (one more SS level)
+template <int W>
+constexpr bool pw_nested() {
+    return W == 1024 || W == 2048;
+}
+
+template <int W>
+constexpr size_t pw_lds_bytes() {
+    if constexpr (pw_nested<W>()) {
+        constexpr size_t n = (size_t)nest::Nest<W>::WORDS, s = (size_t)pw_lds_words(W);
+        return 4 * (n > s ? n : s);  // the special operands take the schoolbook path's layout
+    } else {
+        return (size_t)pw_lds_words(W) * 4;
+    }
+}
+
+template <int W>
+constexpr uint32_t pw_block() {
+    return pw_nested<W>() ? kNestThreads : pw_threads(W);
+}
+
+template <int S, int C, bool TR>
+auto pw_kernel() {
+    if constexpr (pw_nested<S * C>())
+        return &fermat_pointwise_nested_kernel<S, C, TR>;
+    else
+        return &fermat_pointwise_kernel<S, C, TR>;
+}
+
+template <int S, int C, bool TR>
+auto pw_items_kernel() {
+    if constexpr (pw_nested<S * C>())
+        return &fermat_pointwise_nested_items_kernel<S, C, TR>;
+    else
+        return &fermat_pointwise_items_kernel<S, C, TR>;
+}
+
 template <int S, int C, bool TR>
 hipError_t pointwise_launch(uint64_t n, const uint32_t *a, const uint32_t *b, uint32_t *c, uint64_t cap,
                             uint32_t scale_e, hipStream_t st) {
     constexpr int W = S * C;
-    const size_t lds = (size_t)pw_lds_words(W) * 4;
+    constexpr size_t lds = pw_lds_bytes<W>();
     if (lds > kLdsBudget) return hipErrorInvalidValue;
     static bool attr = false;
-    hipError_t e = pointwise_attr(&fermat_pointwise_kernel<S, C, TR>, lds, attr);
+    auto kern = pw_kernel<S, C, TR>();
+    hipError_t e = pointwise_attr(kern, lds, attr);
     if (e != hipSuccess) return e;
-    const uint64_t per = kMaxGridX / pw_threads(W);
+    const uint64_t per = kMaxGridX / pw_block<W>();
     for (uint64_t i0 = 0; i0 < n; i0 += per) {
         const uint64_t nb = n - i0 < per ? n - i0 : per;
-        hipLaunchKernelGGL((fermat_pointwise_kernel<S, C, TR>), dim3((uint32_t)nb), dim3(pw_threads(W)), lds, st, a, b,
-                           c, cap, scale_e, (uint32_t)i0);
+        hipLaunchKernelGGL(kern, dim3((uint32_t)nb), dim3(pw_block<W>()), lds, st, a, b, c, cap, scale_e, (uint32_t)i0);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -407,16 +668,16 @@ hipError_t pointwise_launch(uint64_t n, const uint32_t *a, const uint32_t *b, ui
 template <int S, int C, bool TR>
 hipError_t pointwise_items_launch(uint64_t nitems, uint32_t *x, uint64_t cap, const uint4 *items, hipStream_t st) {
     constexpr int W = S * C;
-    const size_t lds = (size_t)pw_lds_words(W) * 4;
+    constexpr size_t lds = pw_lds_bytes<W>();
     if (lds > kLdsBudget) return hipErrorInvalidValue;
     static bool attr = false;
-    hipError_t e = pointwise_attr(&fermat_pointwise_items_kernel<S, C, TR>, lds, attr);
+    auto kern = pw_items_kernel<S, C, TR>();
+    hipError_t e = pointwise_attr(kern, lds, attr);
     if (e != hipSuccess) return e;
-    const uint64_t per = kMaxGridX / pw_threads(W);
+    const uint64_t per = kMaxGridX / pw_block<W>();
     for (uint64_t i0 = 0; i0 < nitems; i0 += per) {
         const uint64_t nb = nitems - i0 < per ? nitems - i0 : per;
-        hipLaunchKernelGGL((fermat_pointwise_items_kernel<S, C, TR>), dim3((uint32_t)nb), dim3(pw_threads(W)), lds, st,
-                           x, cap, items + i0);
+        hipLaunchKernelGGL(kern, dim3((uint32_t)nb), dim3(pw_block<W>()), lds, st, x, cap, items + i0);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

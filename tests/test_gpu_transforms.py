@@ -181,7 +181,7 @@ def test_every_top_split_on_gpu():
         _run_itft(512, 6, 77, 50, 43, 1, seed=top, top_l1=top, leaf_log2=2)
 
 
-@pytest.mark.parametrize("N", [32, 64, 512, 4096, 16384, 65536, 131072])
+@pytest.mark.parametrize("N", [32, 64, 512, 4096, 16384, 32768, 65536, 131072])
 def test_pointwise(N):
     ring = O.FermatRing(N)
     rng = random.Random(N)
@@ -200,6 +200,36 @@ def test_pointwise(N):
         expect = O.pointwise(ring, a[:n], b[:n], scale)
         assert fermat_values(*fermat_from_device(dc, N, cap, n)) == expect
         assert fermat_values(*fermat_from_device(da, N, cap, n)) == expect
+
+
+@pytest.mark.parametrize("N", [32768, 65536])
+def test_pointwise_nested_extremes(N):
+    """The sizes whose products take one more Schoenhage-Strassen level (64
+    pieces, inner transforms over Z/(2^N'+1)): operands that make every piece
+    and every inner coefficient as large as it gets, single pieces at either
+    end, runs of all-ones limbs, 0, 1, 2^N - 1, and 2^N, with and without a
+    scale factor, against the oracle's product."""
+    ring = O.FermatRing(N)
+    rng = random.Random(N + 1)
+    top = (1 << N) - 1
+    piece = 1 << (N // 64)
+    a = [top, top, 0, 1, piece - 1, (piece - 1) << (N - N // 64), 1 << (N - 1), ring.p - 1, top]
+    b = [top, rng.getrandbits(N), rng.getrandbits(N), rng.getrandbits(N), (piece - 1) << (N - N // 64),
+         (piece - 1) << (N - N // 64), 1 << (N - 1), top, ring.p - 1]
+    for _ in range(3):
+        v = 0
+        for q in range(N // 32):
+            v |= (0xFFFFFFFF if rng.random() < 0.5 else 0) << (32 * q)
+        a.append(v)
+        b.append(rng.getrandbits(N))
+    n = cap = len(a)
+    for scale in (0, 5):
+        note("pointwise nested extremes N=%d scale=%d" % (N, scale))
+        da, db = fermat_to_device(a, N, cap, torch), fermat_to_device(b, N, cap, torch)
+        dc = torch.zeros_like(da)
+        T.pointwise_mul(T.fermat_ring(N), n, da, db, dc, cap, scale)
+        torch.cuda.synchronize()
+        assert fermat_values(*fermat_from_device(dc, N, cap, n)) == O.pointwise(ring, a, b, scale)
 
 
 # ---------------------------------------------------------------------------
