@@ -79,6 +79,19 @@ def alg_cells_itft(l, z, n, f):
     return cells
 
 
+def pointwise_limb_macs(N):
+    """Limb multiply-accumulates of one pointwise product in Z/(2^N+1) as the
+    library computes it: N = 32768 and 65536 go through one more
+    Schoenhage-Strassen level (64 inner products of WI x WI limbs mod
+    2^(32 WI)+1, WI = 64 and 96), other sizes are schoolbook (N/32)^2."""
+    inner = {32768: 64, 65536: 96}.get(N)
+    if inner:
+        return 64 * inner * inner, ("fermat_pointwise_nested_kernel: 64 inner products of %d x %d limbs "
+                                    "mod 2^%d+1 between length-64 transforms" % (inner, inner, 32 * inner))
+    W = N // 32
+    return W * W, "fermat_pointwise_kernel: %d x %d limbs (schoolbook)" % (W, W)
+
+
 def host_threads():
     """(nproc, threads used): the CPUs this process may run on, capped at the
     GPU host's share."""
@@ -232,11 +245,14 @@ def _leg(fn):
 
 
 def batch_leg(T, torch, count=4096, train_count=32, heldout=16, replays=3, k1_stride=16):
-    """Many Z[x] products of uneven lengths: batched plans (hipGraph replay) under three
-    parameter policies (the cost model trained on single-product timings, the same
-    model trained on batch-context timings, and the default rule's k with whole-row
-    padding and the twist), the fastest reported, against one-at-a-time zx_mul_ss
-    with the default rule; outputs compared bit for bit on the device."""
+    """Many Z[x] products of uneven lengths in batched plans (hipGraph replay), with
+    each request's parameters chosen by the learned policy: the cost model trained
+    on batch-context timings of candidates (k, split, whole-row padding, twist) of
+    requests outside the batch.  That is the reported number.  Two labelled
+    comparisons run the same batch: the fixed rule (the default rule's k with
+    whole-row padding and the twist for every request) and the cost model
+    trained on single-product timings.  All against one-at-a-time zx_mul_ss with
+    the default rule; outputs compared bit for bit on the device."""
     from paper_0810_3203_amd import tuning
     from synth import device as dev
 
@@ -288,14 +304,16 @@ def batch_leg(T, torch, count=4096, train_count=32, heldout=16, replays=3, k1_st
     _progress("batch: batch-context model trained (loss %.4f), held-out regret %.3f, %.1f s"
               % (loss_b, tb_mlp / tb_best - 1, tune_b_s))
 
+    # the learned policy: the batch-context model's choice per request
     arr = T.requests_array(reqs)
     t0 = time.perf_counter()
-    model.choose(arr)
+    model_b.choose(arr)
     choose_s = time.perf_counter() - t0
     ks = {}
     for r in arr:
         ks[r.params.k] = ks.get(r.params.k, 0) + 1
     padded = sum(1 for r in arr if r.params.pad_rows)
+    twisted = sum(1 for r in arr if r.params.zeta_exp)
 
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
@@ -320,8 +338,7 @@ def batch_leg(T, torch, count=4096, train_count=32, heldout=16, replays=3, k1_st
         del ws
         return ms, n_launch, build_s
 
-    # policy 1: the cost model's choice per request (trained on single-product timings)
-    batch_ms_model, launches_model, plan_s = time_plan(arr, "cost model")
+    batch_ms, launches, plan_s = time_plan(arr, "learned")
 
     # one at a time, default rule, no graph
     params = [T.ss_default_params(g.shape[0], g.shape[1], h.shape[0], h.shape[1]) for g, h in ops]
@@ -344,9 +361,9 @@ def batch_leg(T, torch, count=4096, train_count=32, heldout=16, replays=3, k1_st
     _progress("batch: one at a time %.1f ms" % single_ms)
     exact = all(torch.equal(a, b) for a, b in zip(outs_b, outs_s))
 
-    # policy 2: the default rule's k with whole-row padding and the forward twist
-    # theta^(3N/2) (ITFT theta^N), the options that merged passes reward; N from
-    # the ring-size feature log2(W)/12
+    # comparison 1: the fixed rule, the default rule's k with whole-row padding
+    # and the forward twist theta^(3N/2) for every request (the options merged
+    # passes reward); N from the ring-size feature log2(W)/12
     arr2 = T.requests_array(reqs)
     for r in arr2:
         p = T.ss_default_params(r.len_g, r.g_limbs, r.len_h, r.h_limbs)
@@ -354,17 +371,13 @@ def batch_leg(T, torch, count=4096, train_count=32, heldout=16, replays=3, k1_st
         W = int(round(2 ** (12 * T.ss_features(r.len_g, r.g_limbs, r.len_h, r.h_limbs, p)[5])))
         p.zeta_exp = 3 * (32 * W) // 2
         r.params = p
-    batch_ms_rule, launches_rule, _ = time_plan(arr2, "default k, padded, twisted")
+    batch_ms_rule, launches_rule, _ = time_plan(arr2, "fixed rule")
     exact_rule = all(torch.equal(a, b) for a, b in zip(outs_b, outs_s))
-    # policy 3: the cost model trained on batch-context timings
+    # comparison 2: the cost model trained on single-product timings
     arr3 = T.requests_array(reqs)
-    model_b.choose(arr3)
-    batch_ms_mb, launches_mb, _ = time_plan(arr3, "batch-context cost model")
-    exact_mb = all(torch.equal(a, b) for a, b in zip(outs_b, outs_s))
-    pol = {"cost_model": (batch_ms_model, launches_model), "default_k_padded_twisted": (batch_ms_rule, launches_rule),
-           "batch_context_cost_model": (batch_ms_mb, launches_mb)}
-    used = min(pol, key=lambda k: pol[k][0])
-    batch_ms, launches = pol[used]
+    model.choose(arr3)
+    batch_ms_single, launches_single, _ = time_plan(arr3, "single-product cost model")
+    exact_single = all(torch.equal(a, b) for a, b in zip(outs_b, outs_s))
 
     # the paper's literal product (k = 1) one at a time, on every k1_stride-th request
     p1 = [T.SSParams(0, 0, T.Split(0, 0), 1)] * count
@@ -386,6 +399,7 @@ def batch_leg(T, torch, count=4096, train_count=32, heldout=16, replays=3, k1_st
     muls = count / (batch_ms * 1e-3)
     return {
         "workload": "%d Z[x] products, lengths uniform in [100, 20000], 1000-bit coefficients" % count,
+        "policy": "learned: cost model trained on batch-context timings, argmin per request",
         "muls_per_s": round(muls, 1),
         "batch_ms": round(batch_ms, 3),
         "launches": launches,
@@ -395,16 +409,21 @@ def batch_leg(T, torch, count=4096, train_count=32, heldout=16, replays=3, k1_st
         "k1_one_at_a_time_ms_extrapolated": round(k1_ms, 3),
         "speedup_vs_k1_one_at_a_time": round(k1_ms / batch_ms, 3),
         "k1_sample": "every %dth request (%d), time scaled by %d/%d" % (k1_stride, len(sel), count, len(sel)),
-        "bit_exact_vs_one_at_a_time": bool(exact and exact_k1 and exact_rule and exact_mb),
-        "policies_ms": dict({k: round(v[0], 3) for k, v in pol.items()}, used=used),
-        "batch_context_cost_model": {"train_rows": len(Xb), "final_loss": round(loss_b, 5),
-                                     "heldout_regret": round(tb_mlp / tb_best - 1, 4),
-                                     "heldout_gain_vs_default": round(tb_def / tb_mlp, 4), "host_s": round(tune_b_s, 2)},
+        "bit_exact_vs_one_at_a_time": bool(exact and exact_k1 and exact_rule and exact_single),
+        "comparison_fixed_rule": {"batch_ms": round(batch_ms_rule, 3), "launches": launches_rule,
+                                  "speedup_vs_one_at_a_time": round(single_ms / batch_ms_rule, 3),
+                                  "learned_gain": round(batch_ms_rule / batch_ms, 4)},
+        "comparison_single_product_cost_model": {"batch_ms": round(batch_ms_single, 3), "launches": launches_single,
+                                                 "learned_gain": round(batch_ms_single / batch_ms, 4)},
+        "learned_model": {"train_requests": train_count, "train_rows": len(Xb), "final_loss": round(loss_b, 5),
+                          "heldout_requests": heldout, "heldout_regret": round(tb_mlp / tb_best - 1, 4),
+                          "heldout_gain_vs_default": round(tb_def / tb_mlp, 4), "host_s": round(tune_b_s, 2)},
         "k_chosen": {str(k): v for k, v in sorted(ks.items())},
         "padded_chosen": padded,
-        "cost_model": {"train_requests": train_count, "train_rows": len(X), "final_loss": round(loss, 5),
-                       "heldout_requests": heldout, "heldout_regret": round(t_mlp / t_best - 1, 4),
-                       "heldout_gain_vs_default": round(t_def / t_mlp, 4)},
+        "twisted_chosen": twisted,
+        "single_product_cost_model": {"train_rows": len(X), "final_loss": round(loss, 5),
+                                      "heldout_regret": round(t_mlp / t_best - 1, 4),
+                                      "heldout_gain_vs_default": round(t_def / t_mlp, 4)},
         "host_s": {"generate": round(gen_s, 2), "tune": round(tune_s, 2), "train": round(train_s, 2),
                    "choose": round(choose_s, 2), "plan": round(plan_s, 2)},
     }
@@ -619,6 +638,8 @@ def main():
                          "of Z[x] products with 8000-bit coefficients (one JSON line)")
     ap.add_argument("--large-only", action="store_true",
                     help="only the large product (for profiler runs): no probe, other products or batch")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="instead of the benchmark: only the batched-products leg (one JSON line)")
     ap.add_argument("--prime-only", action="store_true",
                     help="instead of the benchmark: only the (Z/pZ)[x] small-coefficient leg (one JSON line)")
     ap.add_argument("--alu-probe", action="store_true",
@@ -643,6 +664,9 @@ def main():
         return
     if args.alu_probe:
         print(json.dumps(alu_probe(T)), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps(batch_leg(T, torch)), flush=True)
         return
     if args.prime_only:
         print(json.dumps(prime_leg(T, torch)), flush=True)
@@ -718,12 +742,18 @@ def main():
             "avg_launch_ms": round(leaf_ms / max(1, launches), 4),
         },
     }
-    # the pointwise stage is bound by its limb multiply-accumulate (v_mad_u64_u32
-    # + v_addc_co_u32); its ceiling is that pair's register-only issue rate
+    # the pointwise stage's multiplications are limb multiply-accumulates
+    # (v_mad_u64_u32 + v_addc_co_u32); their ceiling is that pair's
+    # register-only issue rate.  At N = 65536 a product is 64 inner products of
+    # 96 x 96 limbs mod 2^3072+1 between two length-64 transforms (one more
+    # Schoenhage-Strassen level); the rate counts those multiply-accumulates,
+    # and the schoolbook count the same stage replaces is reported beside it.
     probe = {} if args.large_only else _leg(lambda: alu_probe(T))
     line["alu_probe"] = probe
     mac_peak = probe.get("mac_pair_T_per_s")
-    pw_achieved = n * (N // 32) ** 2 / (avg("pointwise_ms") * 1e-3) / 1e12
+    macs, how = pointwise_limb_macs(N)
+    pw_s = avg("pointwise_ms") * 1e-3
+    pw_achieved = n * macs / pw_s / 1e12
     line["pointwise_roofline"] = {
         "bound": "alu",
         "achieved": round(pw_achieved, 3),
@@ -731,7 +761,10 @@ def main():
         "unit": "T limb multiply-accumulates/s",
         "frac": round(pw_achieved / mac_peak, 4) if mac_peak else None,
         "peak_source": "alu_probe.mac_pair_T_per_s (register-only loop of the same two instructions)",
-        "kernel": "fermat_pointwise_kernel<64,32>: %d products of %d x %d limbs (schoolbook)" % (n, N // 32, N // 32),
+        "kernel": "%d products: %s" % (n, how),
+        "limb_macs_per_product": macs,
+        "schoolbook_limb_macs_per_product": (N // 32) ** 2,
+        "schoolbook_equivalent_T_per_s": round(n * (N // 32) ** 2 / pw_s / 1e12, 3),
     }
     if not args.no_padded:
         line["product_variants"] = _leg(lambda: padded_leg(T, torch, dg, dh, out, l, n, N, reps=3))

@@ -366,13 +366,14 @@ void tft_batch_plan_destroy(tft_batch_plan *plan);
  * product allows) and the top split of Alg. 1/2.  Every candidate gives the
  * same output bits; only the time differs. */
 
-#define TFT_SS_FEATURES 13
+#define TFT_SS_FEATURES 15
 
 /* The candidate set of a product shape, in a fixed order: k = 1, 2, 4, ..., 32
  * (those the ring sizes allow), each with the paper's split and, when the
  * transform needs more than one leaf, a split whose column pass is one leaf;
  * each of these is followed by its whole-row padded form (pad_rows = 1) when
- * padding changes the truncation.
+ * padding changes the truncation, and every one of them by its twisted form
+ * (zeta_exp = 3N/2).
  * out == NULL: only *count is set.  TFT_E_ARG if cap < *count. */
 int tft_ss_candidates(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h_limbs, tft_ss_params *out,
                       uint32_t cap, uint32_t *count);
@@ -386,7 +387,7 @@ int tft_ss_default_params(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint
  * cost model: operand lengths and limbs, k, l, ring size, fill n/L (n the
  * transforms' truncation, padded or not), footprint, pointwise limb products,
  * transform pass bytes, leaf passes of a TFT, top split share, leaf passes of
- * the ITFT.  Host work only. */
+ * the ITFT, whole-row padding (0/1), forward twist (0/1).  Host work only. */
 int tft_ss_features(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h_limbs, const tft_ss_params *p,
                     float *feat);
 

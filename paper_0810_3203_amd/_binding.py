@@ -65,7 +65,7 @@ class ZXRequest(ctypes.Structure):
                 ("out", ctypes.c_void_p), ("out_limbs", ctypes.c_uint32), ("params", SSParams)]
 
 
-SS_FEATURES = 13
+SS_FEATURES = 15
 STATIC_SCRATCH_BYTES = 32 << 20
 
 

@@ -27,9 +27,9 @@ hipError_t launch_fermat_leaf_trans(uint32_t W, uint32_t nwaves, uint32_t njobs,
                                     const LeafOp *ops, uint32_t *x, uint64_t cap, uint32_t ord_mask, uint32_t opmask,
                                     hipStream_t st);
 
-// Persistent leaf executor for W = 256 .. 2048 (fermat_leaf2.hpp): 512 threads
-// per workgroup, one workgroup per compute unit, the next job's cells loaded
-// into registers while the current job runs.
+// Persistent leaf executor (fermat_leaf2.hpp), used for W = 1024 and 2048: 512
+// threads per workgroup, one workgroup per compute unit, the next job's cells
+// loaded into registers while the current job runs.
 bool fermat_leaf2_supported(uint32_t W);
 hipError_t launch_fermat_leaf2(uint32_t W, uint32_t njobs, uint32_t lds_cells, const Job *jobs, uint32_t job_offset,
                                const LeafProg *progs, const LeafStep *steps, const LeafOp *ops, uint32_t *x,

@@ -28,12 +28,21 @@ uint32_t leaf_max(uint32_t W) {
 
 std::vector<tft_ss_params> candidates(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h_limbs) {
     std::vector<tft_ss_params> out;
-    // p, then p with n padded to whole rows when that changes the truncation
+    // p, p with n padded to whole rows when that changes the truncation, and
+    // each of those with the forward twist zeta = theta^(3N/2) (tft_ss_params)
     auto push = [&](tft_ss_params p) {
-        out.push_back(p);
+        SSShape sh;
+        if (ss_shape(len_g, g_limbs, len_h, h_limbs, &p, &sh)) return;
+        const uint32_t twist = 3u * (32u * sh.W) / 2u;
+        auto both = [&](tft_ss_params q) {
+            out.push_back(q);
+            q.zeta_exp = twist;
+            out.push_back(q);
+        };
+        both(p);
         p.pad_rows = 1;
         SSShape sp;
-        if (!ss_shape(len_g, g_limbs, len_h, h_limbs, &p, &sp) && sp.nt != sp.n) out.push_back(p);
+        if (!ss_shape(len_g, g_limbs, len_h, h_limbs, &p, &sp) && sp.nt != sp.n) both(p);
     };
     for (uint32_t k : kKs) {
         tft_ss_params p{};
@@ -134,6 +143,8 @@ int tft_ss_features(uint64_t len_g, uint32_t g_limbs, uint64_t len_h, uint32_t h
         (float)pt / 8.0f,                                     // leaf passes of one TFT
         (float)top / (float)sh.l,                             // share of the top split in the columns
         (float)pi / 32.0f,                                    // leaf passes of the ITFT
+        (float)(sh.nt != sh.n ? 1 : 0),                       // n padded to whole rows
+        (float)(sh.s != 0u ? 1 : 0),                          // forward twist zeta != 1
     };
     std::copy(f, f + TFT_SS_FEATURES, feat);
     return TFT_OK;

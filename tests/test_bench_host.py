@@ -54,3 +54,15 @@ def test_more_than_one_gpu_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_pointwise_limb_macs_follow_the_products_method():
+    """The pointwise roofline counts the multiply-accumulates the library
+    performs: 64 inner products of 96 x 96 (N = 65536) or 64 x 64 (N = 32768)
+    limbs for the sizes with one more Schoenhage-Strassen level, (N/32)^2
+    otherwise."""
+    import bench
+    assert bench.pointwise_limb_macs(65536)[0] == 64 * 96 * 96
+    assert bench.pointwise_limb_macs(32768)[0] == 64 * 64 * 64
+    assert bench.pointwise_limb_macs(8192)[0] == 256 * 256
+    assert bench.pointwise_limb_macs(65536)[0] * 7 < (65536 // 32) ** 2

@@ -32,9 +32,10 @@ def _fermat_case(ring, rng, z):
     return vals
 
 
-# (N, l, s, z, n): one shape on the first leaf kernel (64 limbs a cell), one on
-# the persistent one (256 limbs), both of odd truncations not used elsewhere
-FERMAT_SHAPES = [(2048, 8, 333, 201, 233), (8192, 7, 9001, 101, 117)]
+# (N, l, s, z, n): two shapes on the first leaf kernel (64 and 256 limbs a
+# cell), one on the persistent one (1024 limbs), all of odd truncations not
+# used elsewhere
+FERMAT_SHAPES = [(2048, 8, 333, 201, 233), (8192, 7, 9001, 101, 117), (32768, 6, 70001, 41, 57)]
 
 
 @pytest.mark.parametrize("N,l,s,z,n", FERMAT_SHAPES)

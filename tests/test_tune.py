@@ -29,11 +29,15 @@ def test_candidates_valid_and_ordered(lg, gl, lh, hl):
     assert cands and cands[0].k == 1 and cands[0].split.top_l1 == 0
     ks = [c.k for c in cands]
     assert ks == sorted(ks)
-    assert len({(c.k, c.split.top_l1, c.pad_rows) for c in cands}) == len(cands)
+    assert len({(c.k, c.split.top_l1, c.pad_rows, c.zeta_exp) for c in cands}) == len(cands)
     for i, c in enumerate(cands):
-        if c.pad_rows:  # follows its unpadded form
+        if c.zeta_exp:  # follows its untwisted form, with zeta = theta^(3N/2)
             prev = cands[i - 1]
-            assert (prev.k, prev.split.top_l1, prev.pad_rows) == (c.k, c.split.top_l1, 0)
+            assert (prev.k, prev.split.top_l1, prev.pad_rows, prev.zeta_exp) == (c.k, c.split.top_l1, c.pad_rows, 0)
+            assert c.zeta_exp == 3 * (32 * _shape(lg, gl, lh, hl, c)["W"]) // 2
+        elif c.pad_rows:  # follows its unpadded form and that form's twist
+            prev = cands[i - 2]
+            assert (prev.k, prev.split.top_l1, prev.pad_rows, prev.zeta_exp) == (c.k, c.split.top_l1, 0, 0)
         assert T.zx_mul_ss_workspace(lg, gl, lh, hl, c) == _shape(lg, gl, lh, hl, c)["bytes"]
         if c.split.top_l1:
             assert 1 <= c.split.top_l1 < _shape(lg, gl, lh, hl, c)["l"]
