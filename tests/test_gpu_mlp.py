@@ -141,7 +141,10 @@ def test_model_regret_and_gain():
     print("held-out: best %.2f ms, model %.2f ms (regret %.3f), default %.2f ms, k=1 %.2f ms"
           % (t_best, t_mlp, regret, t_def, sum(r["k1"] for r in rows)), flush=True)
     assert regret < 0.25
-    assert t_mlp <= 1.05 * t_def
+    # the trained model must gain over the fixed default rule on requests it
+    # was not trained on (candidates the rule never takes: splits, padding,
+    # the twist); measured about 1.2x
+    assert t_mlp < 0.95 * t_def
     # what the trained model gains over the method without it (one coefficient per
     # ring element, the paper's setting): measured about 1.5x on these requests
     t_k1 = sum(r["k1"] for r in rows)
