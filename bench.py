@@ -81,10 +81,10 @@ def alg_cells_itft(l, z, n, f):
 
 def pointwise_limb_macs(N):
     """Limb multiply-accumulates of one pointwise product in Z/(2^N+1) as the
-    library computes it: N = 32768 and 65536 go through one more
+    library computes it: N = 16384 .. 131072 go through one more
     Schoenhage-Strassen level (64 inner products of WI x WI limbs mod
-    2^(32 WI)+1, WI = 64 and 96), other sizes are schoolbook (N/32)^2."""
-    inner = {32768: 64, 65536: 96}.get(N)
+    2^(32 WI)+1, WI = 32, 64, 96, 160), other sizes are schoolbook (N/32)^2."""
+    inner = {16384: 32, 32768: 64, 65536: 96, 131072: 160}.get(N)
     if inner:
         return 64 * inner * inner, ("fermat_pointwise_nested_kernel: 64 inner products of %d x %d limbs "
                                     "mod 2^%d+1 between length-64 transforms" % (inner, inner, 32 * inner))

@@ -46,6 +46,11 @@ namespace nest {
 
 template <int W>
 struct Cfg;
+// N = 16384: 64 pieces of 256 bits over Z/(2^1024+1) (omega = 2^32, psi = 2^16)
+template <>
+struct Cfg<512> {
+    static constexpr int K = 64, WI = 32;
+};
 // N = 32768: 64 pieces of 512 bits over Z/(2^2048+1) (omega = 2^64, psi = 2^32)
 template <>
 struct Cfg<1024> {
@@ -55,6 +60,11 @@ struct Cfg<1024> {
 template <>
 struct Cfg<2048> {
     static constexpr int K = 64, WI = 96;
+};
+// N = 131072: 64 pieces of 2048 bits over Z/(2^5120+1) (omega = 2^160, psi = 2^80)
+template <>
+struct Cfg<4096> {
+    static constexpr int K = 64, WI = 160;
 };
 
 template <int W_>

@@ -213,10 +213,14 @@ int main() {
             if (scanf("%x", &a[q]) != 1) return 2;
         for (int q = 0; q < W; ++q)
             if (scanf("%x", &b[q]) != 1) return 2;
-        if (W == 1024)
+        if (W == 512)
+            run_case<512>(a, b);
+        else if (W == 1024)
             run_case<1024>(a, b);
         else if (W == 2048)
             run_case<2048>(a, b);
+        else if (W == 4096)
+            run_case<4096>(a, b);
         else
             return 3;
     }

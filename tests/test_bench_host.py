@@ -64,5 +64,6 @@ def test_pointwise_limb_macs_follow_the_products_method():
     import bench
     assert bench.pointwise_limb_macs(65536)[0] == 64 * 96 * 96
     assert bench.pointwise_limb_macs(32768)[0] == 64 * 64 * 64
+    assert bench.pointwise_limb_macs(131072)[0] == 64 * 160 * 160
     assert bench.pointwise_limb_macs(8192)[0] == 256 * 256
     assert bench.pointwise_limb_macs(65536)[0] * 7 < (65536 // 32) ** 2

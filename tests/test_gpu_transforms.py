@@ -202,7 +202,7 @@ def test_pointwise(N):
         assert fermat_values(*fermat_from_device(da, N, cap, n)) == expect
 
 
-@pytest.mark.parametrize("N", [32768, 65536])
+@pytest.mark.parametrize("N", [16384, 32768, 65536, 131072])
 def test_pointwise_nested_extremes(N):
     """The sizes whose products take one more Schoenhage-Strassen level (64
     pieces, inner transforms over Z/(2^N'+1)): operands that make every piece

@@ -2,7 +2,7 @@
 
 tests/native/nested_emu.cpp compiles the functions the kernel's nested
 pointwise product is made of (paper_0810_3203_amd/csrc/fermat_nested.hpp) for
-the host and runs them in the kernel's phase order.  For N = 32768 and 65536
+the host and runs them in the kernel's phase order.  For N = 16384 to 131072
 it gets the per-limb positive and negative word sums the kernel's last phase
 adds up, and this test checks that they give a b mod 2^N+1 (the oracle's
 product in Z/(2^N+1)) for random operands and for the ones that stress the
@@ -57,7 +57,7 @@ def _cases(N, rng):
     return vals
 
 
-@pytest.mark.parametrize("N", [32768, 65536])
+@pytest.mark.parametrize("N", [16384, 32768, 65536, 131072])
 def test_nested_product_emulated(emu_exe, N):
     ring = O.FermatRing(N)
     rng = random.Random(N)
