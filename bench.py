@@ -432,7 +432,8 @@ def batch_leg(T, torch, count=4096, train_count=32, heldout=16, replays=3, k1_st
 def other_products(T, torch, reps=5):
     """Latency of the other product workloads (median of `reps` runs, HIP events on the stream):
     Z[x] 500 x 500 of 64 bits (ring 2^512+1, L = 2^10) and 3000 x 3000 of 2000 bits (2^4096+1, L = 2^13),
-    both latency-bound, and the Schoenhage-Nussbaumer product in (Z/mZ)[x], 500000 x 500000, K = 1024."""
+    both latency-bound and reported against their launch floor (launches x one back-to-back launch),
+    and the Schoenhage-Nussbaumer product in (Z/mZ)[x], 500000 x 500000, K = 1024."""
     import numpy as np
     from synth import workloads as wl
 
@@ -449,7 +450,20 @@ def other_products(T, torch, reps=5):
             ts.append(e0.elapsed_time(e1))
         return sorted(ts)[len(ts) // 2]
 
-    out = {}
+    # the floor of a launch-bound product: its kernel launches (pack of g and h,
+    # the leaf passes, the pointwise products, unpack) times the time of one
+    # back-to-back launch of a trivial kernel on the same stream
+    one = torch.zeros(1, device="cuda")
+    one.add_(1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(200):
+        one.add_(1)
+    e1.record()
+    torch.cuda.synchronize()
+    launch_ms = e0.elapsed_time(e1) / 200
+    out = {"launch_ms": round(launch_ms, 5)}
     for c in (1, 2):
         g, h = wl.zx_operands(c)
         dg = torch.from_numpy(g.view(np.int32)).cuda()
@@ -458,8 +472,11 @@ def other_products(T, torch, reps=5):
         o = torch.empty((g.shape[0] + h.shape[0] - 1, ow), dtype=torch.int32, device="cuda")
         ws = torch.empty(T.zx_mul_ss_workspace(g.shape[0], g.shape[1], h.shape[0], h.shape[1]), dtype=torch.uint8,
                          device="cuda")
-        out["zx_%dx%d_%dbit_ms" % (g.shape[0], h.shape[0], wl.ZX_CASES[c]["bits"])] = round(
-            timed(lambda: T.zx_mul_ss(dg, dh, o, ws=ws)), 4)
+        ms = timed(lambda: T.zx_mul_ss(dg, dh, o, ws=ws))
+        launches = T.zx_mul_ss_timed(dg, dh, o, ws=ws)["leaf_launches"] + 4
+        out["zx_%dx%d_%dbit" % (g.shape[0], h.shape[0], wl.ZX_CASES[c]["bits"])] = {
+            "ms": round(ms, 4), "launches": launches, "launch_floor_ms": round(launches * launch_ms, 4),
+            "frac_of_launch_floor": round(launches * launch_ms / ms, 3)}
     m, g, h = wl.zmx_operands()
     dg = torch.from_numpy(g.view(np.int64)).cuda()
     dh = torch.from_numpy(h.view(np.int64)).cuda()
