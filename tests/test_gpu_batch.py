@@ -148,6 +148,32 @@ def test_batch_matches_oracle_and_single(coracle):
         assert np.array_equal(got, r.one_at_a_time()), "request %d vs one-at-a-time" % i
 
 
+def test_batch_nested_pointwise_sizes(coracle):
+    """Batch plans whose rings take the nested pointwise level through the
+    item-list kernel at every size it serves: 1000-bit coefficients bundled
+    k = 4, 8, 16, 32 per element give 512-, 1024-, 2048- and 4096-limb cells;
+    plus one all-ones request.  Against the oracle and one-at-a-time."""
+    reqs = []
+    for i, k in enumerate((4, 8, 16, 32, 16)):
+        lg, lh = 37 + 13 * i, 29 + 7 * i
+        g, h = _operands(777 + i, lg, lh, 1000)
+        if i == 4:
+            g[:] = 0xFFFFFFFF
+            h[:] = 0xFFFFFFFF
+            g[:, -1] = h[:, -1] = (1 << (1000 - 32 * 31)) - 1
+        reqs.append(_Req(g, h, T.SSParams(0, 0, T.Split(0, 0), k)))
+    plan = T.BatchPlan([r.req for r in reqs])
+    assert plan.status() == [0] * len(reqs)
+    ws = torch.empty(max(1, plan.workspace), dtype=torch.uint8, device="cuda")
+    note("batch plan of nested pointwise sizes: %d launches" % plan.launches)
+    plan.execute(ws)
+    torch.cuda.synchronize()
+    for i, r in enumerate(reqs):
+        got = r.result()
+        assert np.array_equal(got, _oracle_full(coracle, r)), "request %d vs oracle" % i
+        assert np.array_equal(got, r.one_at_a_time()), "request %d vs one-at-a-time" % i
+
+
 def test_batch_graph_replays():
     reqs = _mixed_requests(seed=7)
     plan = T.BatchPlan([r.req for r in reqs])
