@@ -366,11 +366,7 @@ def batch_leg(T, torch, count=4096, train_count=32, heldout=16, replays=3, k1_st
     # passes reward); N from the ring-size feature log2(W)/12
     arr2 = T.requests_array(reqs)
     for r in arr2:
-        p = T.ss_default_params(r.len_g, r.g_limbs, r.len_h, r.h_limbs)
-        p.pad_rows = 1
-        W = int(round(2 ** (12 * T.ss_features(r.len_g, r.g_limbs, r.len_h, r.h_limbs, p)[5])))
-        p.zeta_exp = 3 * (32 * W) // 2
-        r.params = p
+        r.params = tuning.rule_params(r)
     batch_ms_rule, launches_rule, _ = time_plan(arr2, "fixed rule")
     exact_rule = all(torch.equal(a, b) for a, b in zip(outs_b, outs_s))
     # comparison 2: the cost model trained on single-product timings

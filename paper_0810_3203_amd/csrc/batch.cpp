@@ -4,10 +4,11 @@
 // Requests are grouped by ring size W (one kernel instantiation per W).  A
 // group owns one cell array holding, per request, the transform of g and the
 // transform of h.  Pass p of every request's TFT(g) and TFT(h) (Alg. 1) runs in
-// one leaf-kernel launch, the pointwise products of all requests run in one
-// launch over an item list, and pass p of every ITFT (Alg. 2) runs in one
-// launch: the launch count no longer grows with the number of requests.  The
-// whole launch sequence can be captured once into a hipGraph and replayed.
+// a few leaf-kernel launches (one per work-group shape class), the pointwise
+// products of all requests run in one launch over an item list, and pass p of
+// every ITFT (Alg. 2) runs likewise: the launch count no longer grows with the
+// number of requests.  The whole launch sequence can be captured once into a
+// hipGraph and replayed.
 // Requests whose workspace would exceed the caller's limit are split into
 // consecutive chunks that reuse the same workspace.
 #include <hip/hip_runtime.h>
@@ -285,33 +286,61 @@ int tft_batch_plan_create(const tft_zx_request *reqs_in, uint32_t count, uint64_
                 si.push_back(&sched(1, s.l, (uint32_t)((2ull * s.s) % ord), s.nt, s.nt, top, leaf));
             }
             const uint32_t G64 = 64u / std::min<uint32_t>(G.W, 64u);
+            // Pass p of every request runs in launches of its own, one per
+            // class of work-group shape: the cells of the pass's longest job
+            // (rounded up to a power of two) and the waves its largest step
+            // needs.  One launch sizes LDS and waves for its largest job, so a
+            // few long or wide programs in a launch would otherwise slow every
+            // job beside them; a class of fewer than kMinClassJobs jobs joins
+            // the next larger one instead of taking a launch of its own.
             auto merge = [&](std::vector<Pass> &out, const std::vector<std::vector<const std::pair<Schedule, uint32_t> *>> &lists,
                              const std::vector<std::vector<uint64_t>> &offs) {
+                constexpr size_t kMinClassJobs = 512;
+                struct Class {
+                    std::vector<Job> jobs;
+                    uint32_t max_len = 0, max_ops = 0, opmask = 0;
+                };
                 size_t np = 0;
                 for (const auto &lst : lists)
                     for (const auto *s : lst) np = std::max(np, s->first.passes.size());
                 for (size_t p = 0; p < np; p++) {
-                    Pass ps{(uint32_t)G.jobs.size(), 0, 0, 1, 0};
-                    uint32_t max_ops = 0;
+                    std::map<std::pair<uint32_t, uint32_t>, Class> classes;
                     for (size_t li = 0; li < lists.size(); li++) {
                         for (size_t q = 0; q < lists[li].size(); q++) {
                             const Schedule &S = lists[li][q]->first;
                             if (p >= S.passes.size()) continue;
                             const PassDesc &pd = S.passes[p];
+                            if (!pd.job_count) continue;
+                            uint32_t len2 = 1;
+                            while (len2 < pd.max_len) len2 <<= 1;
+                            const uint32_t waves = std::min<uint32_t>(8, std::max<uint32_t>(1, (pd.max_ops + G64 - 1) / G64));
+                            Class &K = classes[{len2, waves}];
                             for (uint32_t j = 0; j < pd.job_count; j++) {
                                 Job jb = S.jobs[pd.job_begin + j];
                                 jb.base += offs[li][q];
                                 jb.prog += lists[li][q]->second;
-                                G.jobs.push_back(jb);
+                                K.jobs.push_back(jb);
                             }
-                            ps.max_len = std::max(ps.max_len, pd.max_len);
-                            ps.opmask |= pd.opmask;
-                            max_ops = std::max(max_ops, pd.max_ops);
+                            K.max_len = std::max(K.max_len, pd.max_len);
+                            K.max_ops = std::max(K.max_ops, pd.max_ops);
+                            K.opmask |= pd.opmask;
                         }
                     }
-                    ps.job_count = (uint32_t)G.jobs.size() - ps.job_begin;
-                    ps.nwaves = std::min<uint32_t>(8, std::max<uint32_t>(1, (max_ops + G64 - 1) / G64));
-                    if (ps.job_count) out.push_back(ps);
+                    Class carry;
+                    size_t left = classes.size();
+                    for (auto &kc : classes) {
+                        Class &K = kc.second;
+                        carry.jobs.insert(carry.jobs.end(), K.jobs.begin(), K.jobs.end());
+                        carry.max_len = std::max(carry.max_len, K.max_len);
+                        carry.max_ops = std::max(carry.max_ops, K.max_ops);
+                        carry.opmask |= K.opmask;
+                        if (--left && carry.jobs.size() < kMinClassJobs) continue;
+                        Pass ps{(uint32_t)G.jobs.size(), (uint32_t)carry.jobs.size(), carry.max_len, 1, carry.opmask};
+                        ps.nwaves = std::min<uint32_t>(8, std::max<uint32_t>(1, (carry.max_ops + G64 - 1) / G64));
+                        G.jobs.insert(G.jobs.end(), carry.jobs.begin(), carry.jobs.end());
+                        if (ps.job_count) out.push_back(ps);
+                        carry = Class{};
+                    }
                 }
             };
             merge(G.p1, {sg, sh}, {offA, offB});

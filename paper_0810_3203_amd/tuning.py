@@ -41,34 +41,49 @@ def time_candidates_in_batch(reqs, copies=8, replays=2, device="cuda"):
     import torch
     out = []
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def plan_ms(r, c, outs, n):
+        arr = (B.ZXRequest * n)()
+        for i in range(n):
+            q = B.ZXRequest(r.g, r.len_g, r.g_limbs, r.h, r.len_h, r.h_limbs, outs[i].data_ptr(), r.out_limbs)
+            q.params = c
+            arr[i] = q
+        plan = B.BatchPlan(arr)
+        ws = torch.empty(max(1, plan.workspace), dtype=torch.uint8, device=device)
+        plan.execute(ws, use_graph=True)  # direct run + capture
+        plan.execute(ws, use_graph=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(replays):
+            plan.execute(ws, use_graph=True)
+        e1.record()
+        torch.cuda.synchronize()
+        plan.close()
+        del ws
+        return e0.elapsed_time(e1) / replays
+
     for r in reqs:
         cands = B.ss_candidates(r.len_g, r.g_limbs, r.len_h, r.h_limbs)
         n_out = (r.len_g + r.len_h - 1) * r.out_limbs
         outs = [torch.empty(n_out, dtype=torch.int32, device=device) for _ in range(copies)]
         ms = []
         for c in cands:
-            arr = (B.ZXRequest * copies)()
-            for i in range(copies):
-                q = B.ZXRequest(r.g, r.len_g, r.g_limbs, r.h, r.len_h, r.h_limbs, outs[i].data_ptr(), r.out_limbs)
-                q.params = c
-                arr[i] = q
-            plan = B.BatchPlan(arr)
-            ws = torch.empty(max(1, plan.workspace), dtype=torch.uint8, device=device)
-            plan.execute(ws, use_graph=True)  # direct run + capture
-            plan.execute(ws, use_graph=True)
-            torch.cuda.synchronize()
-            e0.record()
-            for _ in range(replays):
-                plan.execute(ws, use_graph=True)
-            e1.record()
-            torch.cuda.synchronize()
-            ms.append(e0.elapsed_time(e1) / (replays * copies))
-            plan.close()
-            del ws
+            ms.append(plan_ms(r, c, outs, copies) / copies)
         best = min(range(len(ms)), key=lambda i: (ms[i], i))
         out.append((cands, ms, best))
         del outs
     return out
+
+
+def rule_params(r):
+    """The fixed batch rule for one request: the default rule's k with whole-row
+    padding and the forward twist theta^(3N/2) (N from the ring-size feature
+    log2(W)/12), the options merged passes reward."""
+    p = B.ss_default_params(r.len_g, r.g_limbs, r.len_h, r.h_limbs)
+    p.pad_rows = 1
+    W = int(round(2 ** (12 * B.ss_features(r.len_g, r.g_limbs, r.len_h, r.h_limbs, p)[5])))
+    p.zeta_exp = 3 * (32 * W) // 2
+    return p
 
 
 def training_rows(reqs, timings):
