@@ -157,6 +157,31 @@ def test_batch_plan_policies_on_host():
     rule.close()
 
 
+def test_batch_plan_launch_classes_on_host():
+    """Pass p of a batch runs one launch per work-group class (leaf length,
+    waves) that holds 512 jobs or more; smaller classes join a larger one.
+    Copies of one request form one class a pass; short requests with different
+    leaves fold into the launches of the deepest one; long requests with
+    different leaves add launches."""
+    def plan_launches(shapes_leaves):
+        arr = _dummy_requests([sh for sh, _ in shapes_leaves])
+        for r, (_, leaf) in zip(arr, shapes_leaves):
+            r.params = T.SSParams(0, 0, T.Split(0, leaf), 1)
+        p = T.BatchPlan(arr)
+        assert p.status() == [0] * len(shapes_leaves)
+        n = p.launches
+        p.close()
+        return n
+
+    big, small = (4000, 2, 4100, 2), (60, 2, 45, 2)
+    one = plan_launches([(big, 3)])
+    assert plan_launches([(big, 3)] * 6) == one
+    deepest = plan_launches([(small, 1)])
+    assert plan_launches([(small, 1), (small, 2), (small, 3), (small, 0)]) == deepest
+    alone = max(plan_launches([(big, leaf)]) for leaf in (2, 3, 4))
+    assert plan_launches([(big, 2), (big, 3), (big, 4)]) > alone
+
+
 def test_static_scratch_product_rejects_oversized_requests():
     """zx_mul_ss_static refuses a request whose cell arrays exceed the static
     scratch before touching the device, and says how much it needed."""

@@ -174,6 +174,45 @@ def test_batch_nested_pointwise_sizes(coracle):
         assert np.array_equal(got, r.one_at_a_time()), "request %d vs one-at-a-time" % i
 
 
+def test_batch_launch_classes(coracle):
+    """Requests of one ring whose passes fall in different work-group classes
+    (leaves of 4, 8 and 16 cells, each class with 512 jobs or more a pass, plus
+    the batch's own leaf and a short request whose small class joins a larger
+    one): pass p then runs in several launches.  Bit for bit against
+    one-at-a-time, on oracle samples, and through a graph replay."""
+    reqs = []
+    for i, leaf in enumerate((2, 3, 4, 0, 2)):
+        lg, lh = (4000, 4100) if i < 4 else (60, 45)
+        g, h = _operands(4242 + i, lg, lh, 64)
+        reqs.append(_Req(g, h, T.SSParams(0, 0, T.Split(0, leaf), 1)))
+    plan = T.BatchPlan([r.req for r in reqs])
+    assert plan.status() == [0] * len(reqs)
+    # the same requests with one leaf size: fewer launches
+    same = [_Req(r.g, r.h, T.SSParams(0, 0, T.Split(0, 0), 1)) for r in reqs]
+    plan1 = T.BatchPlan([r.req for r in same])
+    note("batch launch classes: %d launches (one leaf size: %d)" % (plan.launches, plan1.launches))
+    assert plan.launches > plan1.launches
+    ws = torch.empty(max(1, plan.workspace), dtype=torch.uint8, device="cuda")
+    plan.execute(ws)
+    torch.cuda.synchronize()
+    rng = random.Random(9)
+    for i, r in enumerate(reqs):
+        got = r.result()
+        assert np.array_equal(got, r.one_at_a_time()), "request %d vs one-at-a-time" % i
+        nout = r.g.shape[0] + r.h.shape[0] - 1
+        idx = sorted(set([0, nout - 1] + [rng.randrange(nout) for _ in range(24)]))
+        exp = coracle.zx_coeffs(r.g, r.h, idx, r.ow)
+        assert np.array_equal(got[idx], exp), "request %d vs oracle samples" % i
+    ref = [r.result() for r in reqs]
+    for r in reqs:
+        r.out.zero_()
+    note("batch launch classes: graph replay")
+    plan.execute(ws, use_graph=True)
+    torch.cuda.synchronize()
+    for i, r in enumerate(reqs):
+        assert np.array_equal(r.result(), ref[i]), "graph replay request %d" % i
+
+
 def test_batch_graph_replays():
     reqs = _mixed_requests(seed=7)
     plan = T.BatchPlan([r.req for r in reqs])
