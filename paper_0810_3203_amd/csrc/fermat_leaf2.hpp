@@ -262,16 +262,21 @@ __global__ void __launch_bounds__(512) fermat_leaf2_kernel(const Job *__restrict
         const bool has_next = kn < npacks;
         Pack<PK> pn{0u, 0u, Job{}, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
         uint64_t tin = ~0ull;
-        if (has_next) {
-            pn = pack_at(kn);
+        // The next pack's loads are issued unconditionally: a quad that is no
+        // input of it (or every quad after the last pack) reads the thread's
+        // quad of cell 0 instead, and its value is never used.  A load under a
+        // branch would leave the register a merge of the loaded and the old
+        // value, and the compiler resolves that merge with a copy that waits
+        // for the load, so the loads would complete before the butterflies
+        // start instead of during them.
+        if (has_next) pn = pack_at(kn);
+        tin = top_index(pn, false);
+        pre_top = tops[tin != ~0ull ? tin : 0ull];
 #pragma unroll
-            for (int i = 0; i < QPT; ++i) {
-                CellAt at;
-                if (pack_cell(pn, slot_log2, cell(i), false, at))
-                    pre[i] = *reinterpret_cast<const u32x4 *>(x + qm.global(at));
-            }
-            tin = top_index(pn, false);
-            if (tin != ~0ull) pre_top = tops[tin];
+        for (int i = 0; i < QPT; ++i) {
+            CellAt at;
+            const uint64_t a = pack_cell(pn, slot_log2, cell(i), false, at) ? qm.global(at) : (uint64_t)qm.goff;
+            pre[i] = *reinterpret_cast<const u32x4 *>(x + a);
         }
 
         run_pack<C, PK>(sm, jobs, pk, slot_log2, progs, steps, ops, ord_mask, wave);
