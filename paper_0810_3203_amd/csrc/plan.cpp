@@ -143,6 +143,30 @@ struct Builder {
         if (!left.empty()) out.push_back(std::move(left));
     }
 
+    // The steps above follow the recursion of Alg. 1 / Alg. 2: a phase starts
+    // when the previous one has ended, even where its base cases touch other
+    // cells.  Every base case is moved to the earliest step after the last
+    // base case that touched one of its two cells.  Two base cases that share
+    // a cell keep their order, so the result is the same; base cases on
+    // disjoint cells commute.  A partial ITFT leaf of 16 cells, for instance,
+    // goes from 10 steps of about 3 base cases to fewer, wider ones (fewer
+    // barriers, more waves busy a step).
+    static Steps compact_steps(const Steps &steps) {
+        uint32_t ncell = 0;
+        for (const auto &st : steps)
+            for (const SymOp &o : st) ncell = std::max(ncell, std::max(o.i0, o.i1) + 1u);
+        std::vector<int> last(ncell, -1);
+        Steps out;
+        for (const auto &st : steps)
+            for (const SymOp &o : st) {
+                const int k = std::max(last[o.i0], last[o.i1]) + 1;
+                if ((size_t)k >= out.size()) out.resize((size_t)k + 1);
+                out[(size_t)k].push_back(o);
+                last[o.i0] = last[o.i1] = k;
+            }
+        return out;
+    }
+
     uint32_t get_prog(uint32_t dir, uint32_t len, uint64_t z, uint64_t n, uint32_t f) {
         auto key = std::make_tuple(dir, len, z, n, f);
         auto it = cache.find(key);
@@ -153,6 +177,7 @@ struct Builder {
             leaf_tft(len, z, n, steps, nbase);
         else
             leaf_itft(0, len, 0, 0, z, n, f, steps, nbase);
+        steps = compact_steps(steps);
         LeafProg P;
         P.step_begin = (uint32_t)S->steps.size();
         P.step_count = 0;

@@ -57,7 +57,13 @@ def simulate(sched, ring, x, seed=0):
             step_begin, step_count, ln = progs[prog]
             loc = [x[base + i * stride] if i < nload else _rand(ring, rng) for i in range(ln)]
             for op_begin, op_count in steps[step_begin:step_begin + step_count]:
+                # the base cases of one step run at the same time on the GPU
+                # (one wave each): they must touch disjoint cells
+                touched = set()
                 for code, i0, i1, alog, b in ops[op_begin:op_begin + op_count]:
+                    cells = {i0, i1}
+                    assert not (cells & touched), "base cases of one step share a cell"
+                    touched |= cells
                     e = (s * (1 << alog) + b) % ordv
                     loc[i0], loc[i1] = apply_op(ring, code, loc[i0], loc[i1], e)
             for i in range(nstore):
