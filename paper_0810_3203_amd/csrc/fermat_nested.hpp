@@ -142,21 +142,31 @@ struct Nest {
         r = t & 31u;
     }
     template <class Limb>
+    // Piece limbs [k0, k1) of cell i, k1 - k0 = PL / G: all the limbs they
+    // need (and limb k0 - 1) are read first, in a loop of fixed length, so
+    // that the reads are in flight together instead of one after another.
     TFT_NEST_HD static void split_part(Limb limb, int i, int k0, int k1, int64_t *cell) {
+        constexpr int KP = PL / G;
         int Q;
         uint32_t r;
         twist_of(i, Q, r);
-        uint32_t prev = k0 > 0 ? limb(i * PL + k0 - 1) : 0u;
-        const int kend = k1 == PL ? PL + 1 : k1;
-        for (int s = k0; s < kend; ++s) {
-            const uint32_t cur = s < PL ? limb(i * PL + s) : 0u;
+        uint32_t w[KP + 1];  // w[t] = limb k0 + t - 1 of the piece (0 below limb 0)
+#pragma unroll
+        for (int t = 0; t <= KP; ++t) {
+            const int s = k0 + t - 1;
+            const uint32_t x = limb(i * PL + (s > 0 ? s : 0));
+            w[t] = s >= 0 ? x : 0u;
+        }
+        auto put = [&](int s, uint32_t cur, uint32_t prev) {
             const uint32_t v = (cur << r) | (r ? prev >> (32u - r) : 0u);
-            prev = cur;
             int d = s + Q;
             const bool neg = d >= WI;
             if (neg) d -= WI;
             cell[d] = neg ? -(int64_t)v : (int64_t)v;
-        }
+        };
+#pragma unroll
+        for (int t = 1; t <= KP; ++t) put(k0 + t - 1, w[t], w[t - 1]);
+        if (k1 == PL) put(PL, 0u, w[KP]);  // the bits of the top limb shifted past the piece
     }
     TFT_NEST_HD static void split_zero(int i, int d0, int d1, int64_t *cell) {
         int Q;
