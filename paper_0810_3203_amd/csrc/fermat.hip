@@ -565,6 +565,30 @@ __global__ void fermat_unpack1_kernel(const UnpackDesc *__restrict__ descs, Unpa
     }
 }
 
+// The same for transposed cells whose output row takes most of the cell: one
+// workgroup a coefficient reads its cell contiguously into LDS (rows of 64
+// words padded to 65, so the column reads below hit distinct banks), then
+// writes the output row contiguously.  The plain kernel reads limb i at
+// transposed position tpos(i), 256 bytes from limb i+1, so each of its loads
+// touches a different cache line per lane.
+__global__ void __launch_bounds__(256) fermat_unpack1_rows_kernel(const UnpackDesc *__restrict__ descs,
+                                                                  UnpackDesc inl, const uint32_t *__restrict__ x,
+                                                                  uint64_t cap, uint32_t W) {
+    const UnpackDesc d = descs ? descs[blockIdx.y] : inl;
+    extern __shared__ uint32_t sm[];
+    const uint32_t C = W >> 6;
+    for (uint64_t t = blockIdx.x; t < d.len_out; t += gridDim.x) {
+        const uint64_t cell = d.cell0 + t;
+        const uint32_t *src = x + cell * W;
+        __syncthreads();  // the previous coefficient's reads of sm are done
+        for (uint32_t p = threadIdx.x; p < W; p += blockDim.x) sm[(p >> 6) * 65u + (p & 63u)] = src[p];
+        __syncthreads();
+        uint32_t *o = d.out + t * d.olimbs;
+        for (uint32_t i = threadIdx.x; i < d.olimbs; i += blockDim.x)
+            o[i] = i < W ? sm[(i & (C - 1u)) * 65u + i / C] : (i == W ? x[cap * W + cell] : 0u);
+    }
+}
+
 // Unpack with k > 1: the product cell m holds slots 0..2k-2 of width ws limbs;
 // coefficient t = m k + j is slot j of cell m plus slot j + k of cell m - 1.
 // One wave per coefficient and a lane per limb (64 limbs per round): limb i is
@@ -760,7 +784,12 @@ hipError_t launch_fermat_unpack(uint32_t W, const UnpackDesc *descs, uint32_t nd
     if (ndesc == 0 || max_len == 0) return hipSuccess;
     const uint32_t tr = transposed ? 1u : 0u;
     // about 8 words (coefficients) per thread (wave) for the largest product, as in the pack
-    if (!bundled) {
+    if (!bundled && tr && W >= 128u && 2ull * max_olimbs >= W) {
+        // whole cells through LDS: each output row takes most of its cell
+        const uint64_t blocks = max_len < 16384 ? max_len : 16384;
+        hipLaunchKernelGGL(fermat_unpack1_rows_kernel, dim3((uint32_t)blocks, ndesc), dim3(256),
+                           (size_t)(W / 64u) * 65u * 4u, st, descs, inl, x, cap, W);
+    } else if (!bundled) {
         uint64_t blocks = (max_len * max_olimbs + 2047) / 2048;
         if (blocks > 4096) blocks = 4096;
         hipLaunchKernelGGL(fermat_unpack1_kernel, dim3((uint32_t)blocks, ndesc), dim3(256), 0, st, descs, inl, x, cap,
