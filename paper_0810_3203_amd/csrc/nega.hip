@@ -132,10 +132,24 @@ __global__ void __launch_bounds__(512) nega_leaf_kernel(const Job *__restrict__ 
     const LeafProg P = progs[J.prog];
     const uint32_t tid = threadIdx.x, nthr = blockDim.x;
     constexpr uint32_t KQ = K / 2;  // uint4 chunks per cell
-    for (uint32_t q = tid; q < J.nload * KQ; q += nthr) {
-        const uint32_t cell = q / KQ, off = q % KQ;
-        reinterpret_cast<uint4 *>(smq)[q] =
-            reinterpret_cast<const uint4 *>(x + (J.base + (uint64_t)cell * J.stride) * K)[off];
+    // CB reads of a thread in flight together (a loop that stored each read
+    // into LDS before the next would wait for every read in turn).  Past the
+    // end a thread reads and stores the last chunk again (the same value at
+    // the same place), so neither loop has a branch the reads could sink into.
+    constexpr int CB = 8;
+    const uint32_t total = J.nload * KQ;
+    for (uint32_t q0 = tid; q0 < total; q0 += nthr * CB) {
+        uint4 v[CB];
+        uint32_t qs[CB];
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+            const uint32_t q = q0 + (uint32_t)b * nthr;
+            qs[b] = q < total ? q : total - 1u;
+            const uint32_t cell = qs[b] / KQ, off = qs[b] % KQ;
+            v[b] = reinterpret_cast<const uint4 *>(x + (J.base + (uint64_t)cell * J.stride) * K)[off];
+        }
+#pragma unroll
+        for (int b = 0; b < CB; ++b) reinterpret_cast<uint4 *>(smq)[qs[b]] = v[b];
     }
     __syncthreads();
     NegaSeg<S, R> B;
