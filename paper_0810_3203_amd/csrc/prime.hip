@@ -250,7 +250,11 @@ __global__ void __launch_bounds__(kZpThreads) zp_leaf_kernel(const Job *__restri
         const uint64_t base = (uint64_t)d[1] << 32 | d[0], stride = (uint64_t)d[3] << 32 | d[2];
         return base + (uint64_t)r * stride;
     };
-    // eight loads in flight per thread before their LDS stores
+    // eight loads in flight per thread before their LDS stores.  Loads and
+    // stores are unconditional: an element that is no input reads cell 0 of
+    // job 0 and stores into job 0's pad word (LDS word `slot`, never read),
+    // so that the compiler cannot sink each load into a branch of its own
+    // store, where every load would wait for the one before.
     for (uint32_t e0 = tid; e0 < E; e0 += 8u * kZpThreads) {
         uint32_t v[8], at[8];
 #pragma unroll
@@ -258,12 +262,12 @@ __global__ void __launch_bounds__(kZpThreads) zp_leaf_kernel(const Job *__restri
             const uint32_t e = e0 + u * kZpThreads;
             uint32_t p = 0, r = 0;
             if (e < E) elem(e, p, r);
-            at[u] = e < E && p < count && r < dsc[kDescWords * p + 4] ? p * pitch + r : ~0u;
-            if (at[u] != ~0u) v[u] = x[gaddr(p, r)];
+            const bool in = e < E && p < count && r < dsc[kDescWords * p + 4];
+            at[u] = in ? p * pitch + r : slot;
+            v[u] = x[in ? gaddr(p, r) : gaddr(0u, 0u)];
         }
 #pragma unroll
-        for (uint32_t u = 0; u < 8u; ++u)
-            if (at[u] != ~0u) dat[at[u]] = v[u];
+        for (uint32_t u = 0; u < 8u; ++u) dat[at[u]] = v[u];
     }
     __syncthreads();
 
